@@ -1,0 +1,246 @@
+"""CPU oracle for the exact Matern Gaussian log-likelihood (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never loads it.
+
+The numerics live in ``exageo_oracle.c`` (plain FP64 C, single-threaded per
+dot product, optional OpenMP over independent rows with bitwise-identical
+results).  This module is ctypes marshalling plus:
+
+* ``mle``: maximises the oracle's l(theta) with SciPy's bounded optimisers (a
+  library routine used as a step).  The paper's estimator is a bounded
+  maximisation of eq. (2) over (sigma^2, beta, nu) started at the lower bound
+  (Section 3, Example 2); the optimiser's internal steps are not part of the
+  definition, so any correct bounded optimiser pins the maximiser.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "exageo_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ENOTPD = 0, -1, -2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction, OpenMP rows)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    d, i64, p = ctypes.c_double, ctypes.c_int64, ctypes.c_void_p
+    lib.oracle_besselk.restype = d
+    lib.oracle_besselk.argtypes = [d, d]
+    lib.oracle_besselk_scaled.restype = d
+    lib.oracle_besselk_scaled.argtypes = [d, d]
+    lib.oracle_besselk_dnu.restype = d
+    lib.oracle_besselk_dnu.argtypes = [d, d]
+    lib.oracle_besselk_dnu_scaled.restype = d
+    lib.oracle_besselk_dnu_scaled.argtypes = [d, d]
+    lib.oracle_digamma.restype = d
+    lib.oracle_digamma.argtypes = [d]
+    lib.oracle_matern.restype = d
+    lib.oracle_matern.argtypes = [d, p]
+    lib.oracle_matern_grad.restype = None
+    lib.oracle_matern_grad.argtypes = [d, p, p]
+    lib.oracle_matern_cov.restype = ctypes.c_int
+    lib.oracle_matern_cov.argtypes = [i64, p, p, p, p]
+    lib.oracle_cholesky.restype = ctypes.c_int
+    lib.oracle_cholesky.argtypes = [i64, p, p, p, p, p]
+    lib.oracle_simulate.restype = ctypes.c_int
+    lib.oracle_simulate.argtypes = [i64, p, p, p, p, p, p]
+    lib.oracle_loglik.restype = ctypes.c_int
+    lib.oracle_loglik.argtypes = [i64, p, p, p, p, p, p, p, p]
+    lib.oracle_loglik_grad.restype = ctypes.c_int
+    lib.oracle_loglik_grad.argtypes = [i64, p, p, p, p, p, p, p]
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_set_num_threads.restype = None
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int, info: int = 0):
+        super().__init__(f"oracle status {status} (info {info})")
+        self.status = status
+        self.info = info
+
+
+def set_threads(t: int) -> None:
+    _load().oracle_set_num_threads(int(t))
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def besselk(nu: float, x: float) -> float:
+    return float(_load().oracle_besselk(float(nu), float(x)))
+
+
+def besselk_scaled(nu: float, x: float) -> float:
+    """e^x K_nu(x)."""
+    return float(_load().oracle_besselk_scaled(float(nu), float(x)))
+
+
+def besselk_dnu(nu: float, x: float) -> float:
+    return float(_load().oracle_besselk_dnu(float(nu), float(x)))
+
+
+def besselk_dnu_scaled(nu: float, x: float) -> float:
+    return float(_load().oracle_besselk_dnu_scaled(float(nu), float(x)))
+
+
+def digamma(z: float) -> float:
+    return float(_load().oracle_digamma(float(z)))
+
+
+def matern(r: float, theta) -> float:
+    th = _f64(theta)
+    return float(_load().oracle_matern(float(r), _ptr(th)))
+
+
+def matern_grad(r: float, theta) -> np.ndarray:
+    th = _f64(theta)
+    out = np.zeros(3)
+    _load().oracle_matern_grad(float(r), _ptr(th), _ptr(out))
+    return out
+
+
+def matern_cov(x, y, theta) -> np.ndarray:
+    x, y, th = _f64(x), _f64(y), _f64(theta)
+    n = x.size
+    cov = np.empty((n, n))
+    st = _load().oracle_matern_cov(n, _ptr(x), _ptr(y), _ptr(th), _ptr(cov))
+    if st:
+        raise OracleError(st)
+    return cov
+
+
+def cholesky_packed(x, y, theta) -> np.ndarray:
+    """Packed lower (row-major) Cholesky factor of Sigma(theta)."""
+    x, y, th = _f64(x), _f64(y), _f64(theta)
+    n = x.size
+    L = np.empty(n * (n + 1) // 2)
+    info = ctypes.c_int64(0)
+    st = _load().oracle_cholesky(n, _ptr(x), _ptr(y), _ptr(th), _ptr(L), ctypes.byref(info))
+    if st:
+        raise OracleError(st, info.value)
+    return L
+
+
+def simulate(x, y, theta, e) -> np.ndarray:
+    """z = L e, L = chol(Sigma(theta)): one draw of the zero-mean field."""
+    x, y, th, e = _f64(x), _f64(y), _f64(theta), _f64(e)
+    n = x.size
+    z = np.empty(n)
+    info = ctypes.c_int64(0)
+    st = _load().oracle_simulate(n, _ptr(x), _ptr(y), _ptr(th), _ptr(e), _ptr(z), ctypes.byref(info))
+    if st:
+        raise OracleError(st, info.value)
+    return z
+
+
+def loglik(x, y, z, theta, *, details: bool = False):
+    """l(theta) of eq. (2); raises OracleError on invalid input / non-PD."""
+    x, y, z, th = _f64(x), _f64(y), _f64(z), _f64(theta)
+    n = x.size
+    ll, ld, q = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    info = ctypes.c_int64(0)
+    st = _load().oracle_loglik(n, _ptr(x), _ptr(y), _ptr(z), _ptr(th), ctypes.byref(ll),
+                               ctypes.byref(ld), ctypes.byref(q), ctypes.byref(info))
+    if st:
+        raise OracleError(st, info.value)
+    if details:
+        return ll.value, ld.value, q.value
+    return ll.value
+
+
+def loglik_status(x, y, z, theta):
+    """(status, loglik, info) without raising."""
+    x, y, z, th = _f64(x), _f64(y), _f64(z), _f64(theta)
+    n = x.size
+    ll = ctypes.c_double(0)
+    info = ctypes.c_int64(0)
+    st = _load().oracle_loglik(n, _ptr(x), _ptr(y), _ptr(z), _ptr(th), ctypes.byref(ll),
+                               None, None, ctypes.byref(info))
+    return st, ll.value, info.value
+
+
+def loglik_grad(x, y, z, theta):
+    """(l, grad) with grad = dl/d(sigma^2, beta, nu)."""
+    x, y, z, th = _f64(x), _f64(y), _f64(z), _f64(theta)
+    n = x.size
+    ll = ctypes.c_double(0)
+    g = np.zeros(3)
+    info = ctypes.c_int64(0)
+    st = _load().oracle_loglik_grad(n, _ptr(x), _ptr(y), _ptr(z), _ptr(th), ctypes.byref(ll),
+                                    _ptr(g), ctypes.byref(info))
+    if st:
+        raise OracleError(st, info.value)
+    return ll.value, g
+
+
+def mle(x, y, z, lb, ub, theta0=None, *, use_grad: bool = True, tol: float = 1e-9,
+        max_evals: int = 2000):
+    """Bounded maximiser of the oracle's l(theta) (SciPy L-BFGS-B or Powell).
+
+    Non-PD points are infeasible: the objective returns +inf there (the
+    optimiser then backs off), matching the reading that a singular Sigma has
+    l = -inf.
+    """
+    from scipy.optimize import minimize
+
+    lb, ub = _f64(lb), _f64(ub)
+    th0 = _f64(lb if theta0 is None else theta0)
+
+    def f(t):
+        st, ll, _ = loglik_status(x, y, z, t)
+        return -ll if st == OK else np.inf
+
+    def fg(t):
+        try:
+            ll, g = loglik_grad(x, y, z, t)
+        except OracleError:
+            return 1e300, np.zeros(3)
+        return -ll, -g
+
+    bounds = list(zip(lb, ub))
+    if use_grad:
+        res = minimize(fg, th0, jac=True, method="L-BFGS-B", bounds=bounds,
+                       options={"ftol": tol, "gtol": 1e-10, "maxfun": max_evals})
+    else:
+        res = minimize(f, th0, method="Powell", bounds=bounds,
+                       options={"ftol": tol, "xtol": 1e-10, "maxfev": max_evals})
+    return np.asarray(res.x), -float(res.fun), int(res.nfev)
