@@ -1,0 +1,162 @@
+/*
+ * exageo.h -- C ABI of the MI355X (gfx950) library for exact Gaussian-process
+ * maximum-likelihood estimation with a Matern covariance.
+ *
+ * The operation is the one of the ExaGeoStatR paper (Abdulah et al.,
+ * arXiv 1908.06936), Section 1:
+ *   - covariance, eq. (3):
+ *       Sigma_ij = sigma2 / (2^(nu-1) Gamma(nu)) (r_ij/beta)^nu K_nu(r_ij/beta),
+ *       r_ij = Euclidean distance of the 2-D locations s_i, s_j, Sigma_ii = sigma2;
+ *   - log-likelihood, eq. (2) with zero mean:
+ *       l(theta) = -1/2 (n log 2 pi + log det Sigma + z^T Sigma^-1 z),
+ *     evaluated through a Cholesky factorisation, a triangular solve and the
+ *     determinant (the three operations named after eq. (3));
+ *   - the maximum-likelihood estimate over theta = (sigma2, beta, nu) within
+ *     bounds (Section 2.2, optimisation toolbox; Section 3, Example 2).
+ * The gradient entry point adds the Gaussian score
+ *       dl/dtheta_k = 1/2 a^T dSigma_k a - 1/2 tr(Sigma^-1 dSigma_k),
+ *       a = Sigma^-1 z,
+ * which the paper's derivative-free optimiser does not use.
+ *
+ * Conventions shared by every entry point
+ *   theta      host array of 3 doubles, (sigma2, beta, nu), all > 0, nu <= 15.
+ *   x, y, z    DEVICE pointers to n contiguous doubles (locations and
+ *              observations), caller owned, read only, valid for the call.
+ *   outputs    host memory unless stated otherwise.
+ *   streams    all work is queued on the stream given to exageo_create; a call
+ *              returns after synchronising that stream only when it has to
+ *              hand host scalars back.
+ *   order      results do not depend on the order of the locations: the
+ *              library sorts a private copy along a Morton (Z-order) curve.
+ *   errors     no C++ exception crosses the ABI; every call returns a status.
+ *              exageo_last_error() gives a text for the last failure.
+ *   threads    a context is not thread safe; use one per host thread/stream.
+ */
+#ifndef EXAGEO_H
+#define EXAGEO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t exageo_status;
+
+#define EXAGEO_OK 0
+#define EXAGEO_EINVAL (-1)  /* bad argument; nothing was launched            */
+#define EXAGEO_ENOTPD (-2)  /* a pivot of the Cholesky factor was <= 0       */
+#define EXAGEO_ENOMEM (-3)  /* workspace too small or allocation failed      */
+#define EXAGEO_EDEVICE (-4) /* HIP runtime error (text in exageo_last_error) */
+#define EXAGEO_ENOCONV (-5) /* optimiser hit max_iters before tol            */
+
+/* precision of the factorisation */
+#define EXAGEO_FP64 0  /* every tile in double precision                      */
+#define EXAGEO_MIXED 1 /* diagonal tiles FP64, off-diagonal FP32, and BF16 for
+                          tiles whose location boxes are farther apart than
+                          band_factor * beta (Section 2.1, Fig. 1(d))         */
+
+/* optimiser of exageo_mle */
+#define EXAGEO_DFO 0    /* derivative-free bounded search on l(theta)         */
+#define EXAGEO_LBFGSB 1 /* bounded quasi-Newton on (l, grad l)                */
+
+typedef struct exageo_ctx exageo_ctx;
+
+typedef struct {
+  int64_t n_evals;      /* l(theta) evaluations                          */
+  int64_t n_grad_evals; /* (l, grad) evaluations                         */
+  int64_t iters;        /* optimiser iterations                          */
+  double total_s;       /* wall time of the whole estimation             */
+  double per_eval_s;    /* total_s / (n_evals + n_grad_evals)            */
+  exageo_status status; /* EXAGEO_OK or EXAGEO_ENOCONV                    */
+} exageo_mle_stats;
+
+/* Create a context bound to HIP device `device`, tile size `ts` (a multiple of
+ * 128, at least 128; the paper tunes it, Section 3 Example 2, and uses 960 on
+ * GPUs) and stream `hip_stream` (a hipStream_t, NULL = default stream).
+ * Returns EINVAL for a bad ts or device.  Counterpart of exageostat_init. */
+exageo_status exageo_create(exageo_ctx **ctx, int device, int64_t ts, void *hip_stream);
+
+/* Release the context and any memory the library allocated itself.  Memory
+ * given through exageo_set_workspace stays owned by the caller. */
+void exageo_destroy(exageo_ctx *ctx);
+
+/* Change the stream used by later calls. */
+exageo_status exageo_set_stream(exageo_ctx *ctx, void *hip_stream);
+
+/* Device bytes the library needs for a problem of size n (tile storage,
+ * sorted copies, solve vectors, schedules).  want_grad adds the buffers of the
+ * gradient. */
+size_t exageo_workspace_bytes(int64_t n, int64_t ts, int precision, int want_grad);
+
+/* Hand the library a caller-owned device buffer (e.g. a torch tensor) to use
+ * as its workspace.  It is used by every later call whose need fits in it;
+ * otherwise the call returns ENOMEM.  Pass NULL to return to library-owned
+ * allocation (hipMalloc, grown on demand, freed by exageo_destroy). */
+exageo_status exageo_set_workspace(exageo_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Band of the mixed-precision policy: an off-diagonal tile is stored and
+ * updated in BF16 when the minimum distance between the bounding boxes of its
+ * two location blocks is at least band_factor * beta, else in FP32.
+ * 0 disables BF16 (FP32 off-diagonal only).  Default 3.0.  EINVAL if < 0. */
+exageo_status exageo_set_mixed_policy(exageo_ctx *ctx, double band_factor);
+
+/* Text of the last error of this context ("" if none).  Valid until the next
+ * call on the context. */
+const char *exageo_last_error(const exageo_ctx *ctx);
+
+/* Dense covariance, eq. (3): cov[i + j*ldc] = Sigma(s_i, s_j) for 0 <= i, j < n
+ * in the caller's order (no sorting).  cov is a DEVICE pointer, ldc >= n.
+ * Used to check the generation kernel entry by entry. */
+exageo_status exageo_matern_cov(exageo_ctx *ctx, int64_t n, const double *x, const double *y,
+                                const double theta[3], double *cov, int64_t ldc);
+
+/* Synthetic field (paper Section 3, Example 1): z = L e with L the Cholesky
+ * factor of Sigma(theta) in the library's sorted order, mapped back to the
+ * caller's order; e and z are DEVICE pointers to n doubles (e ~ N(0, I) given
+ * by the caller in caller order).  ENOTPD with *info as for exageo_loglik. */
+exageo_status exageo_simulate(exageo_ctx *ctx, int64_t n, const double *x, const double *y,
+                              const double theta[3], const double *e, double *z, int64_t *info);
+
+/* l(theta), eq. (2).  precision is EXAGEO_FP64 or EXAGEO_MIXED.
+ * On ENOTPD: *loglik = -INFINITY and *info = 1 + the caller index of the
+ * location whose pivot failed first in the sorted factorisation; otherwise
+ * *info = 0.  info may be NULL. */
+exageo_status exageo_loglik(exageo_ctx *ctx, int64_t n, const double *x, const double *y, const double *z,
+                            const double theta[3], int precision, double *loglik, int64_t *info);
+
+/* l(theta) and grad[k] = dl/dtheta_k for theta = (sigma2, beta, nu).
+ * On ENOTPD grad is left untouched. */
+exageo_status exageo_loglik_grad(exageo_ctx *ctx, int64_t n, const double *x, const double *y,
+                                 const double *z, const double theta[3], int precision, double *loglik,
+                                 double grad[3], int64_t *info);
+
+/* Maximum-likelihood estimate within lb <= theta <= ub (host arrays of 3).
+ * theta0 = NULL starts at lb, as the paper's optimisation list does.
+ * tol: stop when successive accepted l values differ by less than tol;
+ * max_iters: limit on evaluations, 0 = unlimited.  method EXAGEO_DFO or
+ * EXAGEO_LBFGSB.  Points where the factorisation fails count as l = -inf.
+ * Returns ENOCONV (results still written) when max_iters stops it. */
+exageo_status exageo_mle(exageo_ctx *ctx, int64_t n, const double *x, const double *y, const double *z,
+                         const double lb[3], const double ub[3], const double *theta0, double tol,
+                         int max_iters, int method, int precision, double theta_hat[3], double *loglik_hat,
+                         exageo_mle_stats *stats);
+
+/* Per-phase timing of the last loglik / loglik_grad call, enabled with
+ * exageo_set_profiling(ctx, 1) (adds HIP events between phases).
+ * out receives up to nmax doubles in this order:
+ *   0 total ms (first to last event), 1 sort+prep ms, 2 generation ms,
+ *   3 Cholesky ms, 4 trailing-update GEMM kernel ms (sum of its launches),
+ *   5 trailing-update GEMM flops, 6 solve+reduce ms, 7 gradient ms,
+ *   8 Cholesky flops (n^3/3 + n^2/2 + n/6 of the padded problem, FP64
+ *   equivalent), 9 number of trailing-update launches, 10 precision used,
+ *   11 fraction of off-diagonal tiles in BF16, 12 fraction in FP32.
+ * Returns the number of values written. */
+int exageo_get_timings(const exageo_ctx *ctx, double *out, int nmax);
+exageo_status exageo_set_profiling(exageo_ctx *ctx, int on);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXAGEO_H */

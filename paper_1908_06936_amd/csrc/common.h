@@ -1,0 +1,185 @@
+// Device-side building blocks shared by the HIP kernels of the library.
+//
+// Layout conventions
+//   * The n x n covariance is padded to npad = NT * ts and stored as its lower
+//     tiles only: tile (i, j), i >= j, is a ts x ts column-major block
+//     (leading dimension ts) at element offset ((i (i + 1) / 2) + j) ts^2.
+//     Padding: Sigma_pp = 1 on padded diagonal entries, 0 elsewhere, which
+//     adds nothing to log det Sigma or to z^T Sigma^-1 z (padded z = 0).
+//   * Every dense product is cut into 128 x 128 output blocks, one per
+//     256-thread workgroup (4 wave64s in a 2 x 2 arrangement, each owning a
+//     64 x 64 sub-block = 4 x 4 MFMA tiles of 16 x 16).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace exg {
+
+constexpr int BLK = 128;        // output block edge
+constexpr int BK = 16;          // k-depth of one LDS stage
+constexpr int LDP = BLK + 2;    // padded LDS row length (doubles)
+constexpr int GEMM_THREADS = 256;
+constexpr int GEMM_LDS = 2 * 2 * BK * LDP;  // doubles: 2 operands x 2 stages
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int64_t tri(int64_t i) { return i * (i + 1) / 2; }
+
+__device__ __forceinline__ double* tile_ptr(double* base, int64_t i, int64_t j, int64_t ts) {
+  return base + (tri(i) + j) * ts * ts;
+}
+
+// Decode p in [0, m(m+1)/2) into (a, b), 0 <= b <= a < m, a ascending with p.
+__device__ __forceinline__ void tri_decode(int64_t p, int64_t* a, int64_t* b) {
+  int64_t r = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while (tri(r + 1) <= p) ++r;
+  while (tri(r) > p) --r;
+  *a = r;
+  *b = p - tri(r);
+}
+
+// v_mfma_f64_16x16x4f64 lane layout (checked on gfx950):
+//   operand X (first):  lane l holds X[l % 16][l / 16]      (16 x 4)
+//   operand Y (second): lane l holds Y[l / 16][l % 16]      (4 x 16)
+//   result D = X Y:     lane l, register r holds D[4 r + l / 16][l % 16]
+__device__ __forceinline__ v4d mfma64(double x, double y, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+}
+
+// One 128 x 128 block of  sum_k Aop(m, k) Bop(n, k)  accumulated into acc.
+//   Aop(m, k) = A[m + k * lda]   (AKC = false, m contiguous)
+//             = A[k + m * lda]   (AKC = true,  k contiguous)
+//   Bop(n, k) likewise with B, ldb, BKC.
+// K must be a multiple of BK; A, B and the leading dimensions must keep
+// 16-byte alignment of every pair of doubles read.
+// acc[i][j] holds output rows m = wr*64 + 16 i + (lane & 15) and columns
+// n = wc*64 + 16 j + 4 r + (lane >> 4), r = 0..3 (wr = wave >> 1, wc = wave & 1);
+// with this assignment the lanes of one store instruction write 16
+// consecutive rows of a column-major output.
+template <bool AKC, bool BKC>
+__device__ __forceinline__ void gemm_blk(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+                                         int64_t ldb, int K, v4d (&acc)[4][4], double* sm) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  double* sA = sm;
+  double* sB = sm + 2 * BK * LDP;
+  d2 ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int idx = t + GEMM_THREADS * s;
+      if (!AKC) {
+        const int kk = idx >> 6, m2 = idx & 63;
+        ra[s] = *(const d2*)(A + 2 * m2 + (int64_t)(k0 + kk) * lda);
+      } else {
+        const int m = idx >> 3, kp = idx & 7;
+        ra[s] = *(const d2*)(A + (k0 + 2 * kp) + (int64_t)m * lda);
+      }
+      if (!BKC) {
+        const int kk = idx >> 6, n2 = idx & 63;
+        rb[s] = *(const d2*)(B + 2 * n2 + (int64_t)(k0 + kk) * ldb);
+      } else {
+        const int n = idx >> 3, kp = idx & 7;
+        rb[s] = *(const d2*)(B + (k0 + 2 * kp) + (int64_t)n * ldb);
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+    double* a = sA + buf * BK * LDP;
+    double* b = sB + buf * BK * LDP;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int idx = t + GEMM_THREADS * s;
+      if (!AKC) {
+        const int kk = idx >> 6, m2 = idx & 63;
+        *(d2*)(a + kk * LDP + 2 * m2) = ra[s];
+      } else {
+        const int m = idx >> 3, kp = idx & 7;
+        a[(2 * kp) * LDP + m] = ra[s].x;
+        a[(2 * kp + 1) * LDP + m] = ra[s].y;
+      }
+      if (!BKC) {
+        const int kk = idx >> 6, n2 = idx & 63;
+        *(d2*)(b + kk * LDP + 2 * n2) = rb[s];
+      } else {
+        const int n = idx >> 3, kp = idx & 7;
+        b[(2 * kp) * LDP + n] = rb[s].x;
+        b[(2 * kp + 1) * LDP + n] = rb[s].y;
+      }
+    }
+  };
+  const int nst = K / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) gload((st + 1) * BK);
+    const double* a = sA + cur * BK * LDP + wr * 64 + (lane & 15);
+    const double* b = sB + cur * BK * LDP + wc * 64 + (lane & 15);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int ko = (kk + (lane >> 4)) * LDP;
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = a[ko + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = b[ko + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(bf[j], af[i], acc[i][j]);
+    }
+    if (st + 1 < nst) sstore(cur ^ 1);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void acc_zero(v4d (&acc)[4][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+}
+
+// C(m, n) = beta * C(m, n) + alpha * acc  on a column-major 128 x 128 block.
+__device__ __forceinline__ void acc_store(double* C, int64_t ldc, const v4d (&acc)[4][4], double alpha, bool beta1) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = wr * 64 + 16 * i + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = wc * 64 + 16 * j + 4 * r + (lane >> 4);
+        double* p = C + m + (int64_t)n * ldc;
+        const double v = alpha * acc[i][j][r];
+        *p = beta1 ? (*p + v) : v;
+      }
+    }
+  }
+}
+
+// Block-wide sum of NV doubles per thread in a fixed order (deterministic).
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* NV * blockDim */) {
+  const int t = threadIdx.x, nt = blockDim.x;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) red[q * nt + t] = v[q];
+  __syncthreads();
+  for (int s = nt >> 1; s > 0; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) red[q * nt + t] += red[q * nt + t + s];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = red[q * nt];
+  __syncthreads();
+}
+
+}  // namespace exg

@@ -1,0 +1,565 @@
+// Host side of the C ABI: context, workspace plan, the step schedule of the
+// likelihood / gradient pipeline and the entry points declared in exageo.h.
+#include "exageo.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdarg>
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "mle.h"
+
+namespace {
+
+constexpr int64_t BLKH = 128;
+constexpr int QNB = 10, QNK = 192, QW = 5;  // quadrature table (matern_dev.h)
+constexpr int NEV = 512;                     // profiling events
+
+struct Plan {
+  int64_t n = 0, ts = 0, NT = 0, T = 0, npad = 0, P = 0;
+  bool grad = false;
+  size_t off_tiles = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
+         off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
+         off_info = 0, off_tmp = 0;
+  size_t bytes = 0;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Plan make_plan(int64_t n, int64_t ts, int want_grad) {
+  Plan p;
+  p.n = n;
+  p.ts = ts;
+  p.NT = (n + ts - 1) / ts;
+  p.T = ts / BLKH;
+  p.npad = p.NT * ts;
+  p.P = 2048;
+  while (p.P < p.npad) p.P <<= 1;
+  p.grad = want_grad != 0;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t tt = (size_t)ts * ts;
+  p.off_tiles = take((size_t)(p.NT * (p.NT + 1) / 2) * tt * 8);
+  p.off_xd = p.grad ? take((size_t)p.NT * tt * 8) : 0;
+  p.off_dinv = take((size_t)p.NT * p.T * BLKH * BLKH * 8);
+  p.off_ld = take((size_t)p.NT * p.T * 8);
+  p.off_xs = take((size_t)p.npad * 8);
+  p.off_ys = take((size_t)p.npad * 8);
+  p.off_zs = take((size_t)p.npad * 8);
+  p.off_yv = take((size_t)p.npad * 8);
+  p.off_av = take((size_t)p.npad * 8);
+  p.off_tmp = take((size_t)p.npad * 8);
+  p.off_perm = take((size_t)p.npad * 4);
+  p.off_keys = take((size_t)p.P * 8);
+  p.off_box = take(8 * 8);
+  p.off_qt = take((size_t)QNB * QNK * QW * 8);
+  p.off_cst = take(8 * 8);
+  p.off_part = take((size_t)(p.grad ? exg::lauum_blocks(ts, p.NT) : 1) * 3 * 8);
+  p.off_out = take(16 * 8);
+  p.off_info = take(8);
+  p.bytes = o;
+  return p;
+}
+
+}  // namespace
+
+struct exageo_ctx {
+  int device = 0;
+  int64_t ts = 768;
+  hipStream_t stream = nullptr;
+  double band_factor = 3.0;
+  bool profiling = false;
+  std::string err;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  // pinned host staging for results
+  double* hres = nullptr;
+  // current plan and sorted-location cache key (only valid inside one call or an MLE run)
+  Plan plan;
+  // profiling
+  hipEvent_t ev[NEV];
+  int nev_created = 0;
+  double timings[16] = {0};
+};
+
+namespace {
+
+exageo_status fail(exageo_ctx* c, exageo_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+exageo_status fail(exageo_ctx* c, exageo_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIPCHK(c, expr)                                                                               \
+  do {                                                                                               \
+    hipError_t e_ = (expr);                                                                          \
+    if (e_ != hipSuccess) return fail((c), EXAGEO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool theta_ok(const double* th) {
+  if (!th) return false;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(th[k]) || !(th[k] > 0.0)) return false;
+  return th[2] <= 15.0;
+}
+
+exageo_status set_device(exageo_ctx* c) {
+  HIPCHK(c, hipSetDevice(c->device));
+  return EXAGEO_OK;
+}
+
+// make sure the workspace holds plan p
+exageo_status ensure_ws(exageo_ctx* c, const Plan& p) {
+  if (c->ws && c->ws_bytes >= p.bytes) return EXAGEO_OK;
+  if (c->ws && !c->ws_owned)
+    return fail(c, EXAGEO_ENOMEM, "workspace of %zu bytes is smaller than the %zu bytes needed", c->ws_bytes,
+                p.bytes);
+  if (c->ws) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, p.bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, EXAGEO_ENOMEM, "hipMalloc(%zu) failed: %s", p.bytes, hipGetErrorString(e));
+  }
+  c->ws = (char*)ptr;
+  c->ws_bytes = p.bytes;
+  c->ws_owned = true;
+  return EXAGEO_OK;
+}
+
+template <typename T>
+T* at(exageo_ctx* c, size_t off) {
+  return reinterpret_cast<T*>(c->ws + off);
+}
+
+void rec(exageo_ctx* c, int i) {
+  if (c->profiling && i < c->nev_created) (void)hipEventRecord(c->ev[i], c->stream);
+}
+
+float ev_ms(exageo_ctx* c, int a, int b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.f;
+  return ms;
+}
+
+// ---------------------------------------------------------------- pipeline
+// Event slots: 0 start, 1 after ordering, 2 after generation, 3 after
+// Cholesky, 4 after solve+reduce, 5 after gradient, 6.. pairs around the
+// trailing-update launches.
+constexpr int EV_UPD0 = 8;
+
+exageo_status prepare_locations(exageo_ctx* c, const Plan& p, const double* x, const double* y, const double* z) {
+  exg::launch_sort_locations(x, y, z, p.n, p.npad, p.P, at<double>(c, p.off_box), at<uint64_t>(c, p.off_keys),
+                             at<double>(c, p.off_xs), at<double>(c, p.off_ys), at<double>(c, p.off_zs),
+                             at<int32_t>(c, p.off_perm), c->stream);
+  HIPCHK(c, hipGetLastError());
+  return EXAGEO_OK;
+}
+
+// Sigma(theta) tiles and their Cholesky factor in place.
+exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
+  double* tiles = at<double>(c, p.off_tiles);
+  exg::launch_quad_table(theta, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
+  exg::launch_fill_info(at<unsigned long long>(c, p.off_info), c->stream);
+  exg::launch_gen_tiles(tiles, p.ts, p.NT, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys),
+                        at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
+  rec(c, 2);
+  double upd_flops = 0.0;
+  int nupd = 0;
+  for (int64_t k = 0; k < p.NT; ++k) {
+    exg::launch_panel(tiles, p.ts, p.NT, k, p.n, at<double>(c, p.off_dinv) + k * p.T * BLKH * BLKH,
+                      at<double>(c, p.off_ld) + k * p.T, at<unsigned long long>(c, p.off_info), c->stream);
+    if (k + 1 < p.NT) {
+      const int slot = EV_UPD0 + 2 * nupd;
+      if (slot + 1 < c->nev_created) rec(c, slot);
+      exg::launch_chol_update(tiles, p.ts, p.NT, k, p.n, c->stream);
+      if (slot + 1 < c->nev_created) rec(c, slot + 1);
+      ++nupd;
+      // algorithmic flops of this update over the real rows
+      for (int64_t j = k + 1; j < p.NT; ++j) {
+        const double rj = (double)std::min<int64_t>(p.ts, p.n - j * p.ts);
+        upd_flops += rj * (rj + 1.0) * (double)p.ts;  // SYRK
+        for (int64_t i = j + 1; i < p.NT; ++i) {
+          const double ri = (double)std::min<int64_t>(p.ts, p.n - i * p.ts);
+          upd_flops += 2.0 * ri * rj * (double)p.ts;
+        }
+      }
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  rec(c, 3);
+  c->timings[5] = upd_flops;
+  c->timings[9] = nupd;
+  return EXAGEO_OK;
+}
+
+exageo_status solve_reduce(exageo_ctx* c, const Plan& p) {
+  double* yv = at<double>(c, p.off_yv);
+  exg::launch_copy(yv, at<double>(c, p.off_zs), p.npad, c->stream);
+  exg::launch_trsv_fwd(at<double>(c, p.off_tiles), p.ts, p.NT, p.n, at<double>(c, p.off_dinv), yv, c->stream);
+  exg::launch_finalize_loglik(yv, p.n, at<double>(c, p.off_ld), p.NT * p.T, at<double>(c, p.off_out), c->stream);
+  HIPCHK(c, hipGetLastError());
+  rec(c, 4);
+  return EXAGEO_OK;
+}
+
+exageo_status gradient(exageo_ctx* c, const Plan& p) {
+  double* tiles = at<double>(c, p.off_tiles);
+  double* av = at<double>(c, p.off_av);
+  exg::launch_copy(av, at<double>(c, p.off_yv), p.npad, c->stream);
+  exg::launch_trsv_bwd(tiles, p.ts, p.NT, at<double>(c, p.off_dinv), av, c->stream);
+  double* Xd = at<double>(c, p.off_xd);
+  exg::launch_diag_inverses(Xd, tiles, at<double>(c, p.off_dinv), p.ts, p.NT, c->stream);
+  for (int64_t k = 0; k < p.NT; ++k)
+    exg::launch_trtri_step(tiles, Xd + k * p.ts * p.ts, p.ts, p.NT, k, p.n, c->stream);
+  exg::launch_lauum_contract(tiles, p.ts, p.NT, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
+                             at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part), c->stream);
+  exg::launch_finalize_grad(at<double>(c, p.off_part), exg::lauum_blocks(p.ts, p.NT), at<double>(c, p.off_out) + 3,
+                            c->stream);
+  HIPCHK(c, hipGetLastError());
+  rec(c, 5);
+  return EXAGEO_OK;
+}
+
+// copy out[0..5] and info to the host and wait
+exageo_status fetch(exageo_ctx* c, const Plan& p, double* out6, int64_t* info_sorted, double* box_flag) {
+  HIPCHK(c, hipMemcpyAsync(c->hres, at<double>(c, p.off_out), 6 * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->hres + 6, at<double>(c, p.off_info), 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->hres + 7, at<double>(c, p.off_box), 5 * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  memcpy(out6, c->hres, 6 * 8);
+  uint64_t inf;
+  memcpy(&inf, c->hres + 6, 8);
+  *info_sorted = (inf == ~(uint64_t)0) ? 0 : (int64_t)inf;
+  if (box_flag) memcpy(box_flag, c->hres + 7, 5 * 8);
+  return EXAGEO_OK;
+}
+
+// caller index + 1 of the sorted column `col1` (1-based)
+int64_t caller_column(exageo_ctx* c, const Plan& p, int64_t col1) {
+  if (col1 <= 0 || col1 > p.n) return col1;
+  int32_t src = -1;
+  if (hipMemcpy(&src, at<int32_t>(c, p.off_perm) + (col1 - 1), 4, hipMemcpyDeviceToHost) != hipSuccess) return col1;
+  return (int64_t)src + 1;
+}
+
+void finish_timings(exageo_ctx* c, const Plan& p, bool grad) {
+  if (!c->profiling) return;
+  (void)hipEventSynchronize(c->ev[grad ? 5 : 4]);
+  c->timings[0] = ev_ms(c, 0, grad ? 5 : 4);
+  c->timings[1] = ev_ms(c, 0, 1);
+  c->timings[2] = ev_ms(c, 1, 2);
+  c->timings[3] = ev_ms(c, 2, 3);
+  double upd = 0.0;
+  for (int i = 0; i < (int)c->timings[9]; ++i) {
+    const int slot = EV_UPD0 + 2 * i;
+    if (slot + 1 < c->nev_created) upd += ev_ms(c, slot, slot + 1);
+  }
+  c->timings[4] = upd;
+  c->timings[6] = ev_ms(c, 3, 4);
+  c->timings[7] = grad ? ev_ms(c, 4, 5) : 0.0;
+  const double n = (double)p.n;
+  c->timings[8] = n * n * n / 3.0 + n * n / 2.0 + n / 6.0;
+}
+
+// box[4] counts non-finite values among x, y and z
+bool inputs_finite(const double box[5]) { return box[4] == 0.0; }
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+exageo_status exageo_create(exageo_ctx** out, int device, int64_t ts, void* hip_stream) {
+  if (!out) return EXAGEO_EINVAL;
+  *out = nullptr;
+  if (ts < BLKH || ts % BLKH != 0 || ts > 4096) return EXAGEO_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return EXAGEO_EINVAL;
+  exageo_ctx* c = new exageo_ctx();
+  c->device = device;
+  c->ts = ts;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void**)&c->hres, 64 * sizeof(double)) != hipSuccess) {
+    delete c;
+    return EXAGEO_EDEVICE;
+  }
+  *out = c;
+  return EXAGEO_OK;
+}
+
+void exageo_destroy(exageo_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->ws && c->ws_owned) (void)hipFree(c->ws);
+  if (c->hres) (void)hipHostFree(c->hres);
+  for (int i = 0; i < c->nev_created; ++i) (void)hipEventDestroy(c->ev[i]);
+  delete c;
+}
+
+exageo_status exageo_set_stream(exageo_ctx* c, void* hip_stream) {
+  if (!c) return EXAGEO_EINVAL;
+  c->stream = (hipStream_t)hip_stream;
+  return EXAGEO_OK;
+}
+
+size_t exageo_workspace_bytes(int64_t n, int64_t ts, int precision, int want_grad) {
+  if (n < 1 || ts < BLKH || ts % BLKH != 0) return 0;
+  (void)precision;
+  return make_plan(n, ts, want_grad).bytes;
+}
+
+exageo_status exageo_set_workspace(exageo_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c) return EXAGEO_EINVAL;
+  if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
+  if (c->ws && c->ws_owned) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipFree(c->ws));
+  }
+  c->ws = (char*)dev_ptr;
+  c->ws_bytes = dev_ptr ? bytes : 0;
+  c->ws_owned = false;
+  return EXAGEO_OK;
+}
+
+exageo_status exageo_set_mixed_policy(exageo_ctx* c, double band_factor) {
+  if (!c || !(band_factor >= 0.0) || !std::isfinite(band_factor)) return EXAGEO_EINVAL;
+  c->band_factor = band_factor;
+  return EXAGEO_OK;
+}
+
+const char* exageo_last_error(const exageo_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+exageo_status exageo_set_profiling(exageo_ctx* c, int on) {
+  if (!c) return EXAGEO_EINVAL;
+  c->profiling = on != 0;
+  if (c->profiling && c->nev_created == 0) {
+    if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
+    for (int i = 0; i < NEV; ++i) {
+      if (hipEventCreate(&c->ev[i]) != hipSuccess) break;
+      c->nev_created = i + 1;
+    }
+  }
+  return EXAGEO_OK;
+}
+
+int exageo_get_timings(const exageo_ctx* c, double* out, int nmax) {
+  if (!c || !out) return 0;
+  int m = nmax < 16 ? nmax : 16;
+  for (int i = 0; i < m; ++i) out[i] = c->timings[i];
+  return m;
+}
+
+exageo_status exageo_matern_cov(exageo_ctx* c, int64_t n, const double* x, const double* y, const double theta[3],
+                                double* cov, int64_t ldc) {
+  if (!c) return EXAGEO_EINVAL;
+  c->err.clear();
+  if (n < 1 || !x || !y || !cov || ldc < n || !theta_ok(theta))
+    return fail(c, EXAGEO_EINVAL, "matern_cov: invalid argument");
+  if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
+  Plan p = make_plan(1, c->ts, 0);
+  exageo_status st = ensure_ws(c, p);
+  if (st) return st;
+  exg::launch_quad_table(theta, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
+  exg::launch_gen_dense(cov, ldc, n, x, y, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EXAGEO_OK;
+}
+
+// evaluation at theta on locations already sorted into the workspace
+static exageo_status eval_sorted(exageo_ctx* c, const Plan& p, const double theta[3], bool want_grad, double* loglik,
+                                 double* grad, int64_t* info, bool check_box) {
+  exageo_status st = factorize(c, p, theta);
+  if (st) return st;
+  st = solve_reduce(c, p);
+  if (st) return st;
+  double out[6], box[5];
+  int64_t inf = 0;
+  st = fetch(c, p, out, &inf, box);
+  if (st) return st;
+  if (check_box && !inputs_finite(box)) return fail(c, EXAGEO_EINVAL, "non-finite location or observation");
+  if (inf != 0 || !std::isfinite(out[0])) {
+    if (inf == 0) {
+      // no non-positive pivot: the non-finite value comes from z
+      return fail(c, EXAGEO_EINVAL, "non-finite likelihood (non-finite observations?)");
+    }
+    if (loglik) *loglik = -INFINITY;
+    if (info) *info = caller_column(c, p, inf);
+    finish_timings(c, p, false);
+    return fail(c, EXAGEO_ENOTPD, "covariance not positive definite at column %lld", (long long)inf);
+  }
+  if (loglik) *loglik = out[0];
+  if (info) *info = 0;
+  if (!want_grad) {
+    finish_timings(c, p, false);
+    return EXAGEO_OK;
+  }
+  st = gradient(c, p);
+  if (st) return st;
+  st = fetch(c, p, out, &inf, nullptr);
+  if (st) return st;
+  if (grad) {
+    grad[0] = out[3];
+    grad[1] = out[4];
+    grad[2] = out[5];
+  }
+  finish_timings(c, p, true);
+  return EXAGEO_OK;
+}
+
+static exageo_status loglik_common(exageo_ctx* c, int64_t n, const double* x, const double* y, const double* z,
+                                   const double theta[3], int precision, double* loglik, double* grad, int64_t* info,
+                                   bool want_grad) {
+  if (!c) return EXAGEO_EINVAL;
+  c->err.clear();
+  if (info) *info = 0;
+  if (n < 1 || !x || !y || !z || !theta_ok(theta) || !loglik || (want_grad && !grad))
+    return fail(c, EXAGEO_EINVAL, "loglik: invalid argument");
+  if (precision != EXAGEO_FP64 && precision != EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "unknown precision");
+  if (precision == EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "mixed precision not available in this build");
+  if (n > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n too large");
+  if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
+  Plan p = make_plan(n, c->ts, want_grad);
+  exageo_status st = ensure_ws(c, p);
+  if (st) return st;
+  c->plan = p;
+  std::memset(c->timings, 0, sizeof c->timings);
+  rec(c, 0);
+  st = prepare_locations(c, p, x, y, z);
+  if (st) return st;
+  rec(c, 1);
+  return eval_sorted(c, p, theta, want_grad, loglik, grad, info, true);
+}
+
+exageo_status exageo_loglik(exageo_ctx* c, int64_t n, const double* x, const double* y, const double* z,
+                            const double theta[3], int precision, double* loglik, int64_t* info) {
+  return loglik_common(c, n, x, y, z, theta, precision, loglik, nullptr, info, false);
+}
+
+exageo_status exageo_loglik_grad(exageo_ctx* c, int64_t n, const double* x, const double* y, const double* z,
+                                 const double theta[3], int precision, double* loglik, double grad[3],
+                                 int64_t* info) {
+  return loglik_common(c, n, x, y, z, theta, precision, loglik, grad, info, true);
+}
+
+exageo_status exageo_simulate(exageo_ctx* c, int64_t n, const double* x, const double* y, const double theta[3],
+                              const double* e, double* z, int64_t* info) {
+  if (!c) return EXAGEO_EINVAL;
+  c->err.clear();
+  if (info) *info = 0;
+  if (n < 1 || !x || !y || !e || !z || !theta_ok(theta)) return fail(c, EXAGEO_EINVAL, "simulate: invalid argument");
+  if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
+  Plan p = make_plan(n, c->ts, 0);
+  exageo_status st = ensure_ws(c, p);
+  if (st) return st;
+  // sorted copy of e goes to zs
+  st = prepare_locations(c, p, x, y, e);
+  if (st) return st;
+  st = factorize(c, p, theta);
+  if (st) return st;
+  double* w = at<double>(c, p.off_tmp);
+  exg::launch_trmv_lower(at<double>(c, p.off_tiles), p.ts, p.NT, p.n, at<double>(c, p.off_zs), w, c->stream);
+  exg::launch_scatter(w, at<int32_t>(c, p.off_perm), p.n, z, c->stream);
+  HIPCHK(c, hipGetLastError());
+  double out[6], box[5];
+  int64_t inf = 0;
+  exg::launch_finalize_loglik(w, p.n, at<double>(c, p.off_ld), p.NT * p.T, at<double>(c, p.off_out), c->stream);
+  st = fetch(c, p, out, &inf, box);
+  if (st) return st;
+  if (!inputs_finite(box)) return fail(c, EXAGEO_EINVAL, "non-finite location or draw");
+  if (inf != 0) {
+    if (info) *info = caller_column(c, p, inf);
+    return fail(c, EXAGEO_ENOTPD, "covariance not positive definite at column %lld", (long long)inf);
+  }
+  return EXAGEO_OK;
+}
+
+exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double* y, const double* z,
+                         const double lb[3], const double ub[3], const double* theta0, double tol, int max_iters,
+                         int method, int precision, double theta_hat[3], double* loglik_hat,
+                         exageo_mle_stats* stats) {
+  if (!c) return EXAGEO_EINVAL;
+  c->err.clear();
+  if (n < 1 || !x || !y || !z || !lb || !ub || !theta_hat || !loglik_hat || !(tol >= 0.0) || max_iters < 0)
+    return fail(c, EXAGEO_EINVAL, "mle: invalid argument");
+  if (method != EXAGEO_DFO && method != EXAGEO_LBFGSB) return fail(c, EXAGEO_EINVAL, "unknown method");
+  if (precision != EXAGEO_FP64 && precision != EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "unknown precision");
+  if (precision == EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "mixed precision not available in this build");
+  for (int k = 0; k < 3; ++k) {
+    if (!theta_ok(lb) || !theta_ok(ub) || lb[k] > ub[k]) return fail(c, EXAGEO_EINVAL, "mle: bad bounds");
+    if (theta0 && (!(theta0[k] >= lb[k]) || !(theta0[k] <= ub[k]))) return fail(c, EXAGEO_EINVAL, "theta0 outside bounds");
+  }
+  if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
+  const bool want_grad = method == EXAGEO_LBFGSB;
+  Plan p = make_plan(n, c->ts, want_grad);
+  exageo_status st = ensure_ws(c, p);
+  if (st) return st;
+  c->plan = p;
+  st = prepare_locations(c, p, x, y, z);
+  if (st) return st;
+  const auto t0 = std::chrono::steady_clock::now();
+  int64_t nev = 0, ngev = 0;
+  exageo_status first_err = EXAGEO_OK;
+  bool checked_box = false;
+  exg::Objective obj = [&](const double th[3], bool g, double* f, double gr[3]) -> bool {
+    double ll = -INFINITY;
+    int64_t inf = 0;
+    exageo_status s = eval_sorted(c, p, th, g, &ll, gr, &inf, !checked_box);
+    checked_box = true;
+    if (g) ++ngev;
+    else ++nev;
+    if (s == EXAGEO_OK) {
+      *f = ll;
+      return true;
+    }
+    if (s != EXAGEO_ENOTPD && first_err == EXAGEO_OK) first_err = s;
+    *f = -INFINITY;
+    return s == EXAGEO_ENOTPD;
+  };
+  double th0[3];
+  for (int k = 0; k < 3; ++k) th0[k] = theta0 ? theta0[k] : lb[k];
+  exg::MleResult res = method == EXAGEO_DFO ? exg::maximize_dfo(obj, lb, ub, th0, tol, max_iters)
+                                            : exg::maximize_lbfgsb(obj, lb, ub, th0, tol, max_iters);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (first_err != EXAGEO_OK) return first_err;
+  for (int k = 0; k < 3; ++k) theta_hat[k] = res.theta[k];
+  *loglik_hat = res.f;
+  if (stats) {
+    stats->n_evals = nev;
+    stats->n_grad_evals = ngev;
+    stats->iters = res.iters;
+    stats->total_s = secs;
+    stats->per_eval_s = (nev + ngev) ? secs / (double)(nev + ngev) : 0.0;
+    stats->status = res.converged ? EXAGEO_OK : EXAGEO_ENOCONV;
+  }
+  if (!std::isfinite(res.f)) return fail(c, EXAGEO_ENOTPD, "no feasible point found");
+  return res.converged ? EXAGEO_OK : fail(c, EXAGEO_ENOCONV, "max_iters reached before tol");
+}
+
+}  // extern "C"

@@ -1,0 +1,319 @@
+// FP64 MFMA kernels of the tile algorithms.  Every kernel maps one 256-thread
+// workgroup to 128 x 128 output blocks and calls the shared gemm_blk core.
+//
+// Cholesky (tile algorithm of Buttari, Langou, Kurzak & Dongarra, Parallel
+// Computing 35, 2009, right-looking over tile columns; the paper relies on it
+// through its tile library, Section 2.2):
+//   panel k: a left-looking sweep over the 128-wide sub-columns c of tile
+//   column k: update, factor the 128 x 128 diagonal block (k_potrf_blk),
+//   then multiply the blocks below by its inverse (TRSM);
+//   trailing update: A_ij -= A_ik A_jk^T for k < j <= i (SYRK on i = j).
+//
+// Inverse L^-1 (tile TRTRI, in place, step k): A_ik <- -A_ik X_kk (i > k);
+// A_ij += A_ik A_kj (i > k > j); A_kj <- X_kk A_kj (j < k); A_kk <- X_kk, with
+// X_kk the inverse of the diagonal tile, itself built from the 128-block
+// inverses by the same four steps on 128-blocks.
+//
+// Fused LAUUM and score contraction: W = L^-T L^-1 = Sigma^-1 block by block,
+// W_IJ = sum_{K >= I} X_KI^T X_KJ, contracted at once with
+//   (a_i a_j / 2 - W_ij / 2) dSigma_m(i, j),  a = Sigma^-1 z,
+// so W is never stored.
+#include "common.h"
+#include "launch.h"
+#include "matern_dev.h"
+
+namespace exg {
+
+// -------------------------------------------------------------- Cholesky
+// trailing update of step k over the tiles (i, j), k < j <= i < NT
+__global__ __launch_bounds__(256, 2) void k_chol_update(double* __restrict__ tiles, int64_t ts, int T, int64_t k,
+                                                        int64_t nreal) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t b = blockIdx.x;
+  const int64_t p = b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  int64_t a, c;
+  tri_decode(p, &a, &c);
+  const int64_t i = k + 1 + a, j = k + 1 + c;
+  if (i == j && u < v) return;
+  if (i * ts + u * BLK >= nreal || j * ts + v * BLK >= nreal) return;  // padding: update is zero
+  const double* A = tile_ptr(tiles, i, k, ts) + u * BLK;
+  const double* B = tile_ptr(tiles, j, k, ts) + v * BLK;
+  double* C = tile_ptr(tiles, i, j, ts) + u * BLK + (int64_t)v * BLK * ts;
+  v4d acc[4][4];
+  acc_zero(acc);
+  gemm_blk<false, false>(A, ts, B, ts, (int)ts, acc, sm);
+  acc_store(C, ts, acc, -1.0, true);
+}
+
+// panel k, sub-column c: rows g0 + blockIdx.x (128-row blocks, global index)
+//   C = A[g, c] -= A[g, 0:c] A[(k,c), 0:c]^T
+__global__ __launch_bounds__(256, 2) void k_panel_update(double* __restrict__ tiles, int64_t ts, int T, int64_t k,
+                                                         int c, int64_t g0) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t g = g0 + blockIdx.x;
+  const int64_t i = g / T;
+  const int u = (int)(g % T);
+  double* P = tile_ptr(tiles, i, k, ts) + u * BLK;
+  const double* D = tile_ptr(tiles, k, k, ts) + c * BLK;
+  v4d acc[4][4];
+  acc_zero(acc);
+  gemm_blk<false, false>(P, ts, D, ts, c * BLK, acc, sm);
+  acc_store(P + (int64_t)c * BLK * ts, ts, acc, -1.0, true);
+}
+
+// panel k, sub-column c: C = A[g, c] Dinv_c^T for the blocks below the diagonal
+// block (in place: each workgroup reads only the block it overwrites)
+__global__ __launch_bounds__(256, 2) void k_panel_trsm(double* __restrict__ tiles, int64_t ts, int T, int64_t k, int c,
+                                                       int64_t g0, const double* __restrict__ dinv) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t g = g0 + blockIdx.x;
+  const int64_t i = g / T;
+  const int u = (int)(g % T);
+  double* C = tile_ptr(tiles, i, k, ts) + u * BLK + (int64_t)c * BLK * ts;
+  v4d acc[4][4];
+  acc_zero(acc);
+  gemm_blk<false, false>(C, ts, dinv, BLK, BLK, acc, sm);
+  acc_store(C, ts, acc, 1.0, false);
+}
+
+// ------------------------------------------- inverses of the diagonal tiles
+// All NT diagonal tiles at once, on copies Xd[k] (ts x ts) that start as the
+// lower part of L_kk; step c of the 128-block algorithm.
+// right: X[r, c] <- -X[r, c] Dinv_c for r > c
+__global__ __launch_bounds__(256, 2) void k_dinv_right(double* __restrict__ Xd, const double* __restrict__ dinv,
+                                                       int64_t ts, int T, int c) {
+  __shared__ double sm[GEMM_LDS];
+  const int nr = T - 1 - c;
+  const int64_t k = blockIdx.x / nr;
+  const int r = c + 1 + (int)(blockIdx.x % nr);
+  double* C = Xd + k * ts * ts + r * BLK + (int64_t)c * BLK * ts;
+  const double* D = dinv + (k * T + c) * BLK * BLK;
+  v4d acc[4][4];
+  acc_zero(acc);
+  gemm_blk<false, true>(C, ts, D, BLK, BLK, acc, sm);  // Bop(n, q) = D(q, n)
+  acc_store(C, ts, acc, -1.0, false);
+}
+
+// gemm: X[r, b] += X[r, c] X[c, b] for r > c > b
+__global__ __launch_bounds__(256, 2) void k_dinv_gemm(double* __restrict__ Xd, int64_t ts, int T, int c) {
+  __shared__ double sm[GEMM_LDS];
+  const int nr = T - 1 - c;
+  const int per = nr * c;
+  const int64_t k = blockIdx.x / per;
+  const int q = (int)(blockIdx.x % per);
+  const int r = c + 1 + q / c, bb = q % c;
+  double* X = Xd + k * ts * ts;
+  v4d acc[4][4];
+  acc_zero(acc);
+  gemm_blk<false, true>(X + r * BLK + (int64_t)c * BLK * ts, ts, X + c * BLK + (int64_t)bb * BLK * ts, ts, BLK, acc,
+                        sm);
+  acc_store(X + r * BLK + (int64_t)bb * BLK * ts, ts, acc, 1.0, true);
+}
+
+// left: X[c, b] <- Dinv_c X[c, b] for b < c (in place)
+__global__ __launch_bounds__(256, 2) void k_dinv_left(double* __restrict__ Xd, const double* __restrict__ dinv,
+                                                      int64_t ts, int T, int c) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t k = blockIdx.x / c;
+  const int bb = (int)(blockIdx.x % c);
+  double* C = Xd + k * ts * ts + c * BLK + (int64_t)bb * BLK * ts;
+  const double* D = dinv + (k * T + c) * BLK * BLK;
+  v4d acc[4][4];
+  acc_zero(acc);
+  gemm_blk<false, true>(D, BLK, C, ts, BLK, acc, sm);  // Aop(m, q) = D(m, q), Bop(n, q) = C(q, n)
+  acc_store(C, ts, acc, 1.0, false);
+}
+
+// --------------------------------------------------------- tile TRTRI step k
+// A_ik <- -A_ik X_kk, i > k: one 128-row strip per workgroup, output column
+// blocks in ascending order (column block c reads columns >= c only).
+__global__ __launch_bounds__(256, 2) void k_tri_right(double* __restrict__ tiles, const double* __restrict__ Xk,
+                                                      int64_t ts, int T, int64_t k, int64_t g0) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t g = g0 + blockIdx.x;
+  const int64_t i = g / T;
+  const int u = (int)(g % T);
+  double* S = tile_ptr(tiles, i, k, ts) + u * BLK;
+  for (int c = 0; c < T; ++c) {
+    v4d acc[4][4];
+    acc_zero(acc);
+    const int64_t off = (int64_t)c * BLK * ts;
+    gemm_blk<false, true>(S + off, ts, Xk + c * BLK + off, ts, (int)(ts - c * BLK), acc, sm);
+    acc_store(S + off, ts, acc, -1.0, false);
+    __syncthreads();
+  }
+}
+
+// A_ij += A_ik A_kj for k < i < NT, 0 <= j < k
+__global__ __launch_bounds__(256, 2) void k_tri_gemm(double* __restrict__ tiles, int64_t ts, int T, int64_t k,
+                                                     int64_t nreal) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t b = blockIdx.x;
+  const int64_t p = b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  const int64_t i = k + 1 + p / k, j = p % k;
+  if (i * ts + u * BLK >= nreal) return;
+  const double* A = tile_ptr(tiles, i, k, ts) + u * BLK;
+  const double* B = tile_ptr(tiles, k, j, ts) + (int64_t)v * BLK * ts;
+  double* C = tile_ptr(tiles, i, j, ts) + u * BLK + (int64_t)v * BLK * ts;
+  v4d acc[4][4];
+  acc_zero(acc);
+  gemm_blk<false, true>(A, ts, B, ts, (int)ts, acc, sm);
+  acc_store(C, ts, acc, 1.0, true);
+}
+
+// A_kj <- X_kk A_kj, j < k: one 128-column strip per workgroup, output row
+// blocks in descending order (row block r reads rows <= r only).
+__global__ __launch_bounds__(256, 2) void k_tri_left(double* __restrict__ tiles, const double* __restrict__ Xk,
+                                                     int64_t ts, int T, int64_t k) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t j = blockIdx.x / T;
+  const int v = (int)(blockIdx.x % T);
+  double* S = tile_ptr(tiles, k, j, ts) + (int64_t)v * BLK * ts;
+  for (int r = T - 1; r >= 0; --r) {
+    v4d acc[4][4];
+    acc_zero(acc);
+    gemm_blk<false, true>(Xk + r * BLK, ts, S, ts, (r + 1) * BLK, acc, sm);
+    acc_store(S + r * BLK, ts, acc, 1.0, false);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------ fused LAUUM + score contraction
+// Block (I, J, u, v) of W = X^T X with X = L^-1 (lower tiles, in place of L),
+// followed by g_m += sum (w_ij (a_i a_j - W_ij) / 2) dSigma_m(i, j) over its
+// entries, w = 2 below the diagonal, 1 on it, 0 above and on padding.
+// part[3 b + m] receives the block's sums (zeros for skipped blocks).
+__global__ __launch_bounds__(256, 2) void k_lauum_contract(const double* __restrict__ X, int64_t ts, int T, int64_t NT,
+                                                           int64_t nreal, const double* __restrict__ xs,
+                                                           const double* __restrict__ ys, const double* __restrict__ av,
+                                                           const double* __restrict__ qt,
+                                                           const double* __restrict__ cst, double* __restrict__ part) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t b = blockIdx.x;
+  const int64_t p = b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  int64_t I, J;
+  tri_decode(p, &I, &J);
+  if ((I == J && u < v) || I * ts + u * BLK >= nreal || J * ts + v * BLK >= nreal) {
+    if (threadIdx.x < 3) part[3 * b + threadIdx.x] = 0.0;
+    return;
+  }
+  v4d acc[4][4];
+  acc_zero(acc);
+  {
+    // K = I: X_II is lower triangular, rows below u*128 only
+    const double* XI = tile_ptr((double*)X, I, I, ts);
+    const double* XJ = tile_ptr((double*)X, I, J, ts);
+    const int64_t r0 = (int64_t)u * BLK;
+    gemm_blk<true, true>(XI + r0 + r0 * ts, ts, XJ + r0 + (int64_t)v * BLK * ts, ts, (int)(ts - r0), acc, sm);
+  }
+  for (int64_t K = I + 1; K < NT; ++K) {
+    if (K * ts >= nreal) break;  // padded rows of X are zero
+    const double* XI = tile_ptr((double*)X, K, I, ts);
+    const double* XJ = tile_ptr((double*)X, K, J, ts);
+    gemm_blk<true, true>(XI + (int64_t)u * BLK * ts, ts, XJ + (int64_t)v * BLK * ts, ts, (int)ts, acc, sm);
+  }
+  // epilogue: regenerate dSigma for this block's entries and contract
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  double g3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t gi = I * ts + u * BLK + wr * 64 + 16 * i + (lane & 15);
+    if (gi >= nreal) continue;
+    const double xi = xs[gi], yi = ys[gi], ai = av[gi];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gj = J * ts + v * BLK + wc * 64 + 16 * j + 4 * r + (lane >> 4);
+        if (gj >= nreal || gj > gi) continue;
+        const double wgt = (gi == gj) ? 0.5 : 1.0;  // (w / 2) with w = 1 or 2
+        const double f = wgt * (ai * av[gj] - acc[i][j][r]);
+        const double dx = xi - xs[gj], dy = yi - ys[gj];
+        double d0, d1, d2;
+        matern_grad(sqrt(dx * dx + dy * dy), cst, qt, &d0, &d1, &d2);
+        g3[0] += f * d0;
+        g3[1] += f * d1;
+        g3[2] += f * d2;
+      }
+    }
+  }
+  __syncthreads();
+  block_sum<3>(g3, sm);
+  if (t == 0) {
+    part[3 * b] = g3[0];
+    part[3 * b + 1] = g3[1];
+    part[3 * b + 2] = g3[2];
+  }
+}
+
+// ------------------------------------------------------------- launchers
+void launch_chol_update(double* tiles, int64_t ts, int64_t NT, int64_t k, int64_t nreal, hipStream_t s) {
+  const int T = (int)(ts / BLK);
+  const int64_t m = NT - k - 1;
+  if (m <= 0) return;
+  const int64_t nblk = m * (m + 1) / 2 * T * T;
+  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, tiles, ts, T, k, nreal);
+}
+
+void launch_panel(double* tiles, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k, double* ldpart_k,
+                  unsigned long long* info, hipStream_t s) {
+  const int T = (int)(ts / BLK);
+  const int64_t gmax = (nreal + BLK - 1) / BLK;  // blocks holding real rows
+  for (int c = 0; c < T; ++c) {
+    const int64_t gd = k * T + c;  // global index of the diagonal block
+    if (c > 0 && gmax > gd)
+      hipLaunchKernelGGL(k_panel_update, dim3((unsigned)(gmax - gd)), dim3(256), 0, s, tiles, ts, T, k, c, gd);
+    double* Dblk = tile_ptr_host(tiles, k, k, ts) + c * BLK + (int64_t)c * BLK * ts;
+    launch_potrf_blk(Dblk, ts, dinv_k + (int64_t)c * BLK * BLK, ldpart_k + c, info, gd * BLK, s);
+    if (gmax > gd + 1)
+      hipLaunchKernelGGL(k_panel_trsm, dim3((unsigned)(gmax - gd - 1)), dim3(256), 0, s, tiles, ts, T, k, c, gd + 1,
+                         dinv_k + (int64_t)c * BLK * BLK);
+  }
+}
+
+void launch_diag_inverses(double* Xd, const double* tiles, const double* dinv, int64_t ts, int64_t NT, hipStream_t s) {
+  const int T = (int)(ts / BLK);
+  launch_copy_diag_lower(Xd, tiles, ts, NT, s);
+  for (int c = 0; c < T; ++c) {
+    if (T - 1 - c > 0)
+      hipLaunchKernelGGL(k_dinv_right, dim3((unsigned)(NT * (T - 1 - c))), dim3(256), 0, s, Xd, dinv, ts, T, c);
+    if (T - 1 - c > 0 && c > 0)
+      hipLaunchKernelGGL(k_dinv_gemm, dim3((unsigned)(NT * (T - 1 - c) * c)), dim3(256), 0, s, Xd, ts, T, c);
+    if (c > 0) hipLaunchKernelGGL(k_dinv_left, dim3((unsigned)(NT * c)), dim3(256), 0, s, Xd, dinv, ts, T, c);
+    launch_put_dinv(Xd, dinv, ts, NT, c, s);
+  }
+}
+
+void launch_trtri_step(double* tiles, const double* Xk, int64_t ts, int64_t NT, int64_t k, int64_t nreal,
+                       hipStream_t s) {
+  const int T = (int)(ts / BLK);
+  const int64_t gmax = (nreal + BLK - 1) / BLK;
+  const int64_t g0 = (k + 1) * T;
+  if (gmax > g0) hipLaunchKernelGGL(k_tri_right, dim3((unsigned)(gmax - g0)), dim3(256), 0, s, tiles, Xk, ts, T, k, g0);
+  if (k > 0 && NT - k - 1 > 0)
+    hipLaunchKernelGGL(k_tri_gemm, dim3((unsigned)((NT - k - 1) * k * T * T)), dim3(256), 0, s, tiles, ts, T, k,
+                       nreal);
+  if (k > 0) hipLaunchKernelGGL(k_tri_left, dim3((unsigned)(k * T)), dim3(256), 0, s, tiles, Xk, ts, T, k);
+  launch_put_diag_tile(tiles, Xk, ts, k, s);
+}
+
+int64_t lauum_blocks(int64_t ts, int64_t NT) {
+  const int64_t T = ts / BLK;
+  return NT * (NT + 1) / 2 * T * T;
+}
+
+void launch_lauum_contract(const double* X, int64_t ts, int64_t NT, int64_t nreal, const double* xs, const double* ys,
+                           const double* av, const double* qt, const double* cst, double* part, hipStream_t s) {
+  const int T = (int)(ts / BLK);
+  hipLaunchKernelGGL(k_lauum_contract, dim3((unsigned)lauum_blocks(ts, NT)), dim3(256), 0, s, X, ts, T, NT, nreal, xs,
+                     ys, av, qt, cst, part);
+}
+
+}  // namespace exg

@@ -1,0 +1,119 @@
+// Covariance generation (paper eq. 3) on the device: per-theta quadrature
+// tables, the packed lower-tile matrix used by the factorisation, and a dense
+// n x n matrix in the caller's order (used to check generation entry by entry).
+#include "common.h"
+#include "launch.h"
+#include "matern_dev.h"
+
+namespace exg {
+
+// psi(z), z > 0: shift with psi(z) = psi(z + 1) - 1/z until z >= 12, then
+// psi(z) ~ ln z - 1/(2z) - sum_k B_2k / (2k z^2k)  (DLMF 5.5.2, 5.11.2).
+__device__ double dev_digamma(double z) {
+  double acc = 0.0;
+  while (z < 12.0) {
+    acc -= 1.0 / z;
+    z += 1.0;
+  }
+  const double iz2 = 1.0 / (z * z);
+  const double s =
+      iz2 * (1.0 / 12 - iz2 * (1.0 / 120 - iz2 * (1.0 / 252 - iz2 * (1.0 / 240 - iz2 * (1.0 / 132 - iz2 * (691.0 / 32760))))));
+  return acc + log(z) - 0.5 / z - s;
+}
+
+// One thread per (bucket m, node k): node t = k h_m, weights of the three
+// integrands including the trapezoidal end weight h/2 at t = 0.
+__global__ void k_quad_table(double s2, double beta, double nu, double* __restrict__ qt, double* __restrict__ cst) {
+  const int m = blockIdx.x, k = threadIdx.x;
+  const double h = 0.2 * exp2(-0.5 * m);
+  const double t = k * h;
+  const double sh = sinh(0.5 * t);
+  const double w = (k == 0) ? 0.5 * h : h;
+  double* q = qt + ((int64_t)m * QNK + k) * QW;
+  q[0] = 2.0 * sh * sh;  // cosh t - 1 without cancellation
+  q[1] = t;
+  q[2] = w * cosh(nu * t);
+  q[3] = w * cosh((nu - 1.0) * t);
+  q[4] = w * t * sinh(nu * t);
+  if (m == 0 && k == 0) {
+    const double c = exp((1.0 - nu) * 0.69314718055994530942 - lgamma(nu));
+    cst[C_S2] = s2;
+    cst[C_BETA] = beta;
+    cst[C_NU] = nu;
+    cst[C_C] = c;
+    cst[C_PSI] = dev_digamma(nu);
+    cst[C_S2C] = s2 * c;
+  }
+}
+
+// Lower tiles of the padded covariance.  One 256-thread block per 128 x 128
+// block (u, v) of tile (I, J); blocks above the diagonal of a diagonal tile
+// are not needed by any later step and are skipped.
+__global__ __launch_bounds__(256) void k_gen_tiles(double* __restrict__ tiles, int64_t ts, int T, int64_t nreal,
+                                                   const double* __restrict__ xs, const double* __restrict__ ys,
+                                                   const double* __restrict__ qt, const double* __restrict__ cst,
+                                                   int64_t tile_first) {
+  const int64_t b = blockIdx.x;
+  const int64_t p = tile_first + b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  int64_t I, J;
+  tri_decode(p, &I, &J);
+  if (I == J && u < v) return;
+  double* tile = tiles + p * ts * ts;
+  const int r = threadIdx.x & 127, c0 = threadIdx.x >> 7;
+  const int64_t gi = I * ts + u * BLK + r;
+  const bool ipad = gi >= nreal;
+  const double xi = ipad ? 0.0 : xs[gi], yi = ipad ? 0.0 : ys[gi];
+  double* out = tile + (u * BLK + r) + (int64_t)(v * BLK) * ts;
+  for (int c = c0; c < BLK; c += 2) {
+    const int64_t gj = J * ts + v * BLK + c;
+    double val;
+    if (ipad || gj >= nreal) {
+      val = (gi == gj) ? 1.0 : 0.0;
+    } else {
+      const double dx = xi - xs[gj], dy = yi - ys[gj];
+      val = matern_value(sqrt(dx * dx + dy * dy), cst, qt);
+    }
+    out[(int64_t)c * ts] = val;
+  }
+}
+
+// cov[i + j ldc] = Sigma(s_i, s_j) in the caller's order.
+__global__ __launch_bounds__(256) void k_gen_dense(double* __restrict__ cov, int64_t ldc, int64_t n,
+                                                   const double* __restrict__ x, const double* __restrict__ y,
+                                                   const double* __restrict__ qt, const double* __restrict__ cst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i];
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+    const double dx = xi - x[j], dy = yi - y[j];
+    cov[i + j * ldc] = matern_value(sqrt(dx * dx + dy * dy), cst, qt);
+  }
+}
+
+void launch_quad_table(const double theta[3], double* qt, double* cst, hipStream_t s) {
+  hipLaunchKernelGGL(k_quad_table, dim3(QNB), dim3(QNK), 0, s, theta[0], theta[1], theta[2], qt, cst);
+}
+
+void launch_gen_tiles(double* tiles, int64_t ts, int64_t NT, int64_t nreal, const double* xs, const double* ys,
+                      const double* qt, const double* cst, hipStream_t s) {
+  const int T = (int)(ts / BLK);
+  const int64_t ntile = NT * (NT + 1) / 2;
+  // keep each launch's grid below 2^31 blocks
+  const int64_t per = (int64_t)1 << 24;
+  for (int64_t f = 0; f < ntile; f += per) {
+    const int64_t cnt = (ntile - f < per) ? ntile - f : per;
+    hipLaunchKernelGGL(k_gen_tiles, dim3((unsigned)(cnt * T * T)), dim3(256), 0, s, tiles, ts, T, nreal, xs, ys, qt,
+                       cst, f);
+  }
+}
+
+void launch_gen_dense(double* cov, int64_t ldc, int64_t n, const double* x, const double* y, const double* qt,
+                      const double* cst, hipStream_t s) {
+  const unsigned gx = (unsigned)((n + 255) / 256);
+  const unsigned gy = (unsigned)(n < 8192 ? n : 8192);
+  hipLaunchKernelGGL(k_gen_dense, dim3(gx, gy), dim3(256), 0, s, cov, ldc, n, x, y, qt, cst);
+}
+
+}  // namespace exg

@@ -1,0 +1,106 @@
+// Matern covariance (paper eq. 3) and its theta-derivatives on the device.
+//
+//   Sigma(r) = sigma2 c(nu) x^nu K_nu(x),   x = r / beta,   c(nu) = 2^(1-nu) / Gamma(nu)
+//
+// K_nu comes from its integral form  K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt
+// (DLMF 10.32.9), evaluated as  e^-x * T(x)  with the trapezoidal rule
+//   T(x) = h [ f(0)/2 + sum_{k>=1} f(k h) ],  f(t) = exp(-x (cosh t - 1)) cosh(nu t),
+// which converges geometrically in 1/h for this analytic, doubly decaying
+// integrand (Trefethen & Weideman, SIAM Review 56, 2014).  The step depends on
+// x through 10 buckets, h_m = 0.2 * 2^(-m/2) for x <= 9 * 2^m (h <= 0.6/sqrt(x)),
+// and the sum stops once x (cosh t - 1) - nu t > 45 (terms below e^-45 of the
+// first one).  The same exponentials give K_{nu-1} (weight cosh((nu-1) t)) and
+// dK_nu/dnu (weight t sinh(nu t), the nu-derivative of the integrand), so one
+// set of exp() calls serves all three derivatives:
+//   dSigma/dsigma2 = Sigma / sigma2
+//   dSigma/dbeta   = sigma2 c x^(nu+1) K_{nu-1}(x) / beta        (DLMF 10.29.4, 10.27.3)
+//   dSigma/dnu     = Sigma (-ln 2 - psi(nu) + ln x) + sigma2 c x^nu dK_nu/dnu(x)
+// Sigma(0) = sigma2 and every nu- or beta-derivative vanishes at r = 0; for
+// x > 700 the covariance is below 1e-250 and is returned as 0.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace exg {
+
+constexpr int QNB = 10;     // step buckets
+constexpr int QNK = 192;    // nodes per bucket (reaches t = 38 at h = 0.2)
+constexpr int QW = 5;       // per node: cosh t - 1, t, w0, w1, w2
+constexpr double QCUT = 45.0;
+constexpr double XMAX = 700.0;
+
+// per-theta constants written by the table kernel
+enum { C_S2 = 0, C_BETA, C_NU, C_C, C_PSI, C_S2C, C_COUNT = 8 };
+
+__device__ __forceinline__ int quad_bucket(double x) {
+  if (x <= 9.0) return 0;
+  int m = (int)ceil(log2(x * (1.0 / 9.0)));
+  return m < QNB - 1 ? m : QNB - 1;
+}
+
+// T0 = e^x K_nu(x)
+__device__ __forceinline__ double quad_k0(const double* __restrict__ qt, double x, double nu) {
+  const double* q = qt + quad_bucket(x) * QNK * QW;
+  double s = 0.0;
+  for (int k = 0; k < QNK; ++k, q += QW) {
+    const double c = q[0];
+    if (k > 0 && x * c - nu * q[1] > QCUT) break;
+    s += exp(-x * c) * q[2];
+  }
+  return s;
+}
+
+// (e^x K_nu, e^x K_{nu-1}, e^x dK_nu/dnu)
+__device__ __forceinline__ void quad_k3(const double* __restrict__ qt, double x, double nu, double* s0, double* s1,
+                                        double* s2) {
+  const double* q = qt + quad_bucket(x) * QNK * QW;
+  double a = 0.0, b = 0.0, c2 = 0.0;
+  for (int k = 0; k < QNK; ++k, q += QW) {
+    const double c = q[0];
+    if (k > 0 && x * c - nu * q[1] > QCUT + 5.0) break;
+    const double e = exp(-x * c);
+    a += e * q[2];
+    b += e * q[3];
+    c2 += e * q[4];
+  }
+  *s0 = a;
+  *s1 = b;
+  *s2 = c2;
+}
+
+__device__ __forceinline__ double matern_value(double r, const double* __restrict__ cst, const double* __restrict__ qt) {
+  if (r == 0.0) return cst[C_S2];
+  const double x = r / cst[C_BETA];
+  if (x > XMAX) return 0.0;
+  const double nu = cst[C_NU];
+  return cst[C_S2C] * pow(x, nu) * exp(-x) * quad_k0(qt, x, nu);
+}
+
+// d[0..2] = dSigma/d(sigma2, beta, nu) at distance r
+__device__ __forceinline__ void matern_grad(double r, const double* __restrict__ cst, const double* __restrict__ qt,
+                                            double* d0, double* d1, double* d2) {
+  if (r == 0.0) {
+    *d0 = 1.0;
+    *d1 = 0.0;
+    *d2 = 0.0;
+    return;
+  }
+  const double beta = cst[C_BETA];
+  const double x = r / beta;
+  if (x > XMAX) {
+    *d0 = 0.0;
+    *d1 = 0.0;
+    *d2 = 0.0;
+    return;
+  }
+  const double nu = cst[C_NU];
+  double t0, t1, t2;
+  quad_k3(qt, x, nu, &t0, &t1, &t2);
+  const double P = cst[C_S2C] * pow(x, nu) * exp(-x);
+  const double sig = P * t0;
+  *d0 = sig / cst[C_S2];
+  *d1 = P * x * t1 / beta;
+  *d2 = sig * (-0.69314718055994530942 - cst[C_PSI] + log(x)) + P * t2;
+}
+
+}  // namespace exg

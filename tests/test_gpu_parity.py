@@ -1,0 +1,272 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerances (written here, derived in the design doc):
+  * covariance entries: relative 2e-13 (trapezoidal K_nu vs Temme/recurrence);
+  * l(theta) in FP64: relative 1e-10;
+  * gradient in FP64: relative 1e-8 of the gradient norm;
+  * exact identities at full size (1-D Markov model, block additivity): 1e-10.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import inputgen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+LN2PI = math.log(2 * math.pi)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+@pytest.fixture(scope="module")
+def exa():
+    import paper_1908_06936_amd as exa
+
+    return exa
+
+
+@pytest.fixture(scope="module")
+def ctx256(exa):
+    return exa.Context(ts=256)
+
+
+@pytest.fixture(scope="module")
+def ctx768(exa):
+    return exa.Context(ts=768)
+
+
+# ------------------------------------------------------------ generation
+@pytest.mark.parametrize("nu", [0.5, 1.0, 1.7, 3.2])
+@pytest.mark.parametrize("beta", [0.03, 0.1, 0.3])
+def test_matern_cov_entries(orc, ctx256, nu, beta):
+    x, y = inputgen.jittered_grid(18, seed=1)
+    x[5], y[5] = x[9], y[9]  # one coincident pair: r = 0 off the diagonal
+    th = [1.3, beta, nu]
+    ref = orc.matern_cov(x, y, th)
+    got = ctx256.matern_cov(dev(x), dev(y), th).cpu().numpy()
+    err = np.abs(got - ref)
+    assert np.all(err <= 2e-13 * np.abs(ref) + 1e-300), f"max rel err {np.max(err / np.maximum(ref, 1e-300))}"
+
+
+def test_matern_cov_small_and_large_distances(orc, ctx256):
+    # distances from 1e-9 to beyond the underflow of exp(-x)
+    t = np.concatenate([[0.0], np.logspace(-9, 2.5, 200)])
+    x, y = t, np.zeros_like(t)
+    for nu in [0.05, 0.5, 2.5, 5.0]:
+        th = [1.0, 0.1, nu]
+        ref = orc.matern_cov(x, y, th)[0]
+        got = ctx256.matern_cov(dev(x), dev(y), th).cpu().numpy()[0]
+        err = np.abs(got - ref)
+        assert np.all(err <= 2e-13 * np.abs(ref) + 1e-250)
+
+
+# ------------------------------------------------------------ likelihood
+@pytest.mark.parametrize("n,ts,nu", [(1, 256, 0.5), (7, 128, 1.0), (300, 128, 0.5), (1000, 256, 1.0),
+                                     (1500, 128, 1.7), (2100, 512, 0.8)])
+def test_loglik_vs_oracle(orc, exa, n, ts, nu):
+    ctx = exa.Context(ts=ts)
+    x, y = inputgen.uniform(n, seed=n)
+    th = [1.0, 0.1, nu]
+    z = orc.simulate(x, y, th, inputgen.normals(n, seed=n)) if n > 1 else np.array([0.7])
+    ref = orc.loglik(x, y, z, th)
+    got = ctx.loglik(dev(x), dev(y), dev(z), th)
+    assert got == pytest.approx(ref, rel=1e-10)
+
+
+@pytest.mark.parametrize("beta", [0.03, 0.1, 0.3])
+@pytest.mark.parametrize("nu", [0.5, 1.0])
+def test_loglik_jittered_grid_vs_oracle(orc, ctx256, beta, nu):
+    x, y = inputgen.jittered_grid(40, seed=2)  # n = 1600, several tiles + ragged tail at ts = 256
+    th = [1.0, beta, nu]
+    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=2))
+    ref = orc.loglik(x, y, z, th)
+    got = ctx256.loglik(dev(x), dev(y), dev(z), th)
+    assert got == pytest.approx(ref, rel=1e-10)
+
+
+def test_loglik_worked_values(exa):
+    ctx = exa.Context(ts=128)
+    assert ctx.loglik(dev([0.0]), dev([0.0]), dev([0.7]), [2, 0.1, 0.5]) == pytest.approx(-1.3880121234846454,
+                                                                                           rel=1e-14)
+    assert ctx.loglik(dev([0, 0.1]), dev([0, 0]), dev([1, 0.5]), [1, 0.1, 0.5]) == pytest.approx(
+        -2.2752643321336263, rel=1e-13)
+    assert ctx.loglik(dev([0, 0.1, 0]), dev([0, 0, 0.2]), dev([1, -0.5, 0.25]), [1.5, 0.1, 1.5]) == pytest.approx(
+        -4.325813976873814, rel=1e-13)
+
+
+def _markov_1d(n, s2, beta, seed):
+    t, y0 = inputgen.collinear(n, mean_gap=0.004, seed=seed)
+    rho = np.exp(-np.diff(t) / beta)
+    e = inputgen.normals(n, seed=seed)
+    z = np.empty(n)
+    z[0] = math.sqrt(s2) * e[0]
+    for i in range(1, n):
+        z[i] = rho[i - 1] * z[i - 1] + math.sqrt(s2 * (1 - rho[i - 1] ** 2)) * e[i]
+    v = s2 * (1 - rho ** 2)
+    ref = -0.5 * (LN2PI + math.log(s2) + z[0] ** 2 / s2)
+    ref += np.sum(-0.5 * (LN2PI + np.log(v) + (z[1:] - rho * z[:-1]) ** 2 / v))
+    return t, y0, z, ref
+
+
+@pytest.mark.parametrize("n", [5000, 40000])
+def test_loglik_markov_full_size(ctx768, n):
+    # nu = 1/2 on a line: exact O(n) likelihood at the full tile shape
+    t, y0, z, ref = _markov_1d(n, 1.2, 0.1, seed=n)
+    perm = inputgen.shuffled(n, seed=3)
+    got = ctx768.loglik(dev(t[perm]), dev(y0[perm]), dev(z[perm]), [1.2, 0.1, 0.5])
+    assert got == pytest.approx(ref, rel=1e-10)
+
+
+def test_loglik_block_additivity(orc, ctx768):
+    # clusters 1000 beta apart: cross-covariances underflow to exactly 0
+    x, y, lab = inputgen.clusters(1500, 4, width=1.0, separation=200.0, seed=7)
+    th = [1.0, 0.1, 1.0]
+    z = np.zeros(x.size)
+    ref = 0.0
+    for c in range(4):
+        m = lab == c
+        z[m] = orc.simulate(x[m], y[m], th, inputgen.normals(int(m.sum()), seed=10 + c))
+        ref += orc.loglik(x[m], y[m], z[m], th)
+    got = ctx768.loglik(dev(x), dev(y), dev(z), th)
+    assert got == pytest.approx(ref, rel=1e-10)
+
+
+def test_loglik_permutation_and_determinism(orc, ctx256):
+    x, y = inputgen.uniform(900, seed=5)
+    th = [0.8, 0.07, 1.3]
+    z = orc.simulate(x, y, th, inputgen.normals(900, seed=5))
+    a = ctx256.loglik(dev(x), dev(y), dev(z), th)
+    b = ctx256.loglik(dev(x), dev(y), dev(z), th)
+    assert a == b  # bitwise: fixed reduction trees, no float atomics
+    perm = inputgen.shuffled(900, seed=5)
+    c = ctx256.loglik(dev(x[perm]), dev(y[perm]), dev(z[perm]), th)
+    assert c == a  # the library sorts internally: identical sorted problem
+
+
+# ------------------------------------------------------------ gradient
+@pytest.mark.parametrize("n,ts,th", [(700, 256, [1.0, 0.1, 1.0]), (1200, 128, [1.4, 0.05, 0.6]),
+                                     (500, 512, [0.9, 0.2, 2.2])])
+def test_grad_vs_oracle(orc, exa, n, ts, th):
+    ctx = exa.Context(ts=ts)
+    x, y = inputgen.uniform(n, seed=n + 1)
+    z = orc.simulate(x, y, th, inputgen.normals(n, seed=n + 1))
+    ll_ref, g_ref = orc.loglik_grad(x, y, z, th)
+    ll, g = ctx.loglik_grad(dev(x), dev(y), dev(z), th)
+    assert ll == pytest.approx(ll_ref, rel=1e-10)
+    assert np.linalg.norm(np.array(g) - g_ref) <= 1e-8 * np.linalg.norm(g_ref)
+
+
+def test_grad_variance_closed_form(orc, ctx256):
+    x, y = inputgen.jittered_grid(30, seed=4)
+    th = [1.6, 0.12, 1.2]
+    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=4))
+    _, _, q = orc.loglik(x, y, z, th, details=True)
+    ll, g = ctx256.loglik_grad(dev(x), dev(y), dev(z), th)
+    assert g[0] == pytest.approx((q - x.size) / (2 * th[0]), rel=1e-10)
+
+
+def test_grad_markov_full_size(ctx768):
+    # nu = 1/2 on a line: dl/dsigma2 and dl/dbeta of the exact O(n) likelihood
+    n, s2, beta = 20000, 1.2, 0.1
+    t, y0, z, _ = _markov_1d(n, s2, beta, seed=9)
+    d = np.diff(t)
+
+    def ref_ll(s2_, b_):
+        rho = np.exp(-d / b_)
+        v = s2_ * (1 - rho ** 2)
+        return -0.5 * (LN2PI + math.log(s2_) + z[0] ** 2 / s2_) + np.sum(
+            -0.5 * (LN2PI + np.log(v) + (z[1:] - rho * z[:-1]) ** 2 / v))
+
+    # analytic derivatives of the factorised density
+    rho = np.exp(-d / beta)
+    v = s2 * (1 - rho ** 2)
+    r = z[1:] - rho * z[:-1]
+    dll_ds2 = -0.5 / s2 + 0.5 * z[0] ** 2 / s2 ** 2 + np.sum(-0.5 / s2 + 0.5 * r ** 2 / (v * s2))
+    drho = rho * d / beta ** 2
+    dv = -2 * s2 * rho * drho
+    dll_db = np.sum(-0.5 * dv / v + r * z[:-1] * drho / v + 0.5 * r ** 2 * dv / v ** 2)
+    h = 1e-6
+    assert dll_ds2 == pytest.approx((ref_ll(s2 + h, beta) - ref_ll(s2 - h, beta)) / (2 * h), rel=1e-5)
+    ll, g = ctx768.loglik_grad(dev(t), dev(y0), dev(z), [s2, beta, 0.5])
+    assert ll == pytest.approx(ref_ll(s2, beta), rel=1e-10)
+    assert g[0] == pytest.approx(dll_ds2, rel=1e-8, abs=1e-8 * abs(dll_db))
+    assert g[1] == pytest.approx(dll_db, rel=1e-8)
+
+
+def test_grad_central_differences(orc, ctx256):
+    x, y = inputgen.jittered_grid(20, seed=8)
+    th = np.array([0.9, 0.11, 1.4])
+    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=8))
+    X, Y, Z = dev(x), dev(y), dev(z)
+    _, g = ctx256.loglik_grad(X, Y, Z, list(th))
+    for k in range(3):
+        h = 1e-6 * th[k]
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (ctx256.loglik(X, Y, Z, list(tp)) - ctx256.loglik(X, Y, Z, list(tm))) / (2 * h)
+        assert g[k] == pytest.approx(fd, rel=1e-6)
+
+
+def test_autograd_function(orc, exa, ctx256):
+    x, y = inputgen.uniform(400, seed=12)
+    th = [1.0, 0.1, 0.9]
+    z = orc.simulate(x, y, th, inputgen.normals(400, seed=12))
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    ll = exa.ExaGeoLoglik.apply(theta, dev(x), dev(y), dev(z), ctx256)
+    (2.0 * ll).backward()
+    ll_ref, g_ref = orc.loglik_grad(x, y, z, th)
+    assert ll.item() == pytest.approx(ll_ref, rel=1e-10)
+    assert np.allclose(theta.grad.numpy(), 2.0 * g_ref, rtol=1e-8, atol=1e-8 * np.abs(g_ref).max())
+
+
+# ------------------------------------------------------------ simulation
+def test_simulate_covariance(orc, ctx256):
+    # columns of the map e -> z are M = P^T L_s P with L_s L_s^T = P Sigma P^T,
+    # so M M^T must reproduce Sigma whatever order the library factorises in
+    n = 260
+    x, y = inputgen.uniform(n, seed=13)
+    th = [1.1, 0.15, 1.2]
+    E = np.eye(n)
+    M = np.stack([ctx256.simulate(dev(x), dev(y), th, dev(E[:, k])).cpu().numpy() for k in range(n)], axis=1)
+    S = orc.matern_cov(x, y, th)
+    assert np.allclose(M @ M.T, S, rtol=0, atol=1e-12 * th[0])
+
+
+# ------------------------------------------------------------ statuses
+def test_statuses(exa, ctx256):
+    # coincident pair with sigma2 = 4: second pivot 4 - (4/2)^2 = 0 exactly
+    st, ll, info = ctx256.loglik_status(dev([0.3, 0.3]), dev([0.2, 0.2]), dev([1.0, 0.5]), [4.0, 0.1, 0.5])
+    assert st == exa.ENOTPD and ll == -math.inf and info in (1, 2)
+    x, y = inputgen.jittered_grid(20, seed=0)
+    st, ll, info = ctx256.loglik_status(dev(x), dev(y), dev(inputgen.normals(400)), [1.0, 5.0, 5.0])
+    assert st == exa.ENOTPD and 1 <= info <= 400
+    X, Y, Z = dev(x), dev(y), dev(inputgen.normals(400))
+    for bad in ([0.0, 0.1, 0.5], [1.0, -0.1, 0.5], [1.0, 0.1, 0.0], [math.nan, 0.1, 0.5], [1.0, 0.1, 16.0]):
+        assert ctx256.loglik_status(X, Y, Z, bad)[0] == exa.EINVAL
+    z2 = inputgen.normals(400)
+    z2[17] = math.nan
+    assert ctx256.loglik_status(X, Y, dev(z2), [1.0, 0.1, 0.5])[0] == exa.EINVAL
+    with pytest.raises(exa.ExaGeoError):
+        exa.Context(ts=200)
+
+
+# ------------------------------------------------------------ MLE
+@pytest.mark.parametrize("method", ["dfo", "lbfgsb"])
+def test_mle_config1(orc, ctx768, method):
+    # 20 x 20 jittered grid, theta = (1, 0.1, 0.5), start at lb = 0.001 (paper Example 2)
+    x, y = inputgen.jittered_grid(20, seed=0)
+    th_true = [1.0, 0.1, 0.5]
+    z = orc.simulate(x, y, th_true, inputgen.normals(400, seed=0))
+    lb, ub = [0.001] * 3, [5.0] * 3
+    th, ll, stats = ctx768.mle(dev(x), dev(y), dev(z), lb, ub, tol=1e-7, method=method)
+    th_o, ll_o, _ = orc.mle(x, y, z, [0.01] * 3, [5.0] * 3, theta0=[0.5, 0.3, 0.7])
+    # the GPU estimate's likelihood, checked by the oracle, reaches the oracle optimum
+    assert orc.loglik(x, y, z, th) == pytest.approx(ll, rel=1e-10)
+    assert ll >= ll_o - 1e-3
+    assert stats["status"] == "OK"
