@@ -133,7 +133,8 @@ exageo_status exageo_loglik_grad(exageo_ctx *ctx, int64_t n, const double *x, co
                                  double grad[3], int64_t *info);
 
 /* Maximum-likelihood estimate within lb <= theta <= ub (host arrays of 3).
- * theta0 = NULL starts at lb, as the paper's optimisation list does.
+ * theta0 = NULL starts the derivative-free method at lb, as the paper's
+ * optimisation list does, and the gradient method at sqrt(lb * ub).
  * tol: stop when successive accepted l values differ by less than tol;
  * max_iters: limit on evaluations, 0 = unlimited.  method EXAGEO_DFO or
  * EXAGEO_LBFGSB.  Points where the factorisation fails count as l = -inf.

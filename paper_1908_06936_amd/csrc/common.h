@@ -47,41 +47,45 @@ __device__ __forceinline__ v4d mfma64(double x, double y, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
 }
 
-// One 128 x 128 block of  sum_k Aop(m, k) Bop(n, k)  accumulated into acc.
-//   Aop(m, k) = A[m + k * lda]   (AKC = false, m contiguous)
-//             = A[k + m * lda]   (AKC = true,  k contiguous)
-//   Bop(n, k) likewise with B, ldb, BKC.
-// K must be a multiple of BK; A, B and the leading dimensions must keep
-// 16-byte alignment of every pair of doubles read.
-// acc[i][j] holds output rows m = wr*64 + 16 i + (lane & 15) and columns
-// n = wc*64 + 16 j + 4 r + (lane >> 4), r = 0..3 (wr = wave >> 1, wc = wave & 1);
-// with this assignment the lanes of one store instruction write 16
-// consecutive rows of a column-major output.
-template <bool AKC, bool BKC>
-__device__ __forceinline__ void gemm_blk(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
-                                         int64_t ldb, int K, v4d (&acc)[4][4], double* sm) {
+// One 128 x 128 block of  sum_k Aop(m, k) Bop(n, k)  accumulated into acc,
+// over a virtual k range [0, K) that may run across several tiles.
+//   aptr(k0) returns the address of Aop(0, k0) for a stage starting at k0;
+//   within a stage (BK consecutive k):
+//     Aop(m, k0 + q) = aptr(k0)[m + q * lda]   (AKC = false, m contiguous)
+//                    = aptr(k0)[q + m * lda]   (AKC = true,  k contiguous)
+//   bptr / Bop(n, k) likewise with ldb, BKC.
+// K must be a multiple of BK; every pair of doubles read must be 16-byte
+// aligned.  acc[i][j] holds output rows m = wr*64 + 16 i + (lane & 15) and
+// columns n = wc*64 + 16 j + 4 r + (lane >> 4), r = 0..3 (wr = wave >> 1,
+// wc = wave & 1); with this assignment the lanes of one store instruction
+// write 16 consecutive rows of a column-major output.
+template <bool AKC, bool BKC, class AP, class BP>
+__device__ __forceinline__ void gemm_core(AP aptr, int64_t lda, BP bptr, int64_t ldb, int K, v4d (&acc)[4][4],
+                                          double* sm) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
   double* sA = sm;
   double* sB = sm + 2 * BK * LDP;
   d2 ra[4], rb[4];
   auto gload = [&](int k0) {
+    const double* A = aptr(k0);
+    const double* B = bptr(k0);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int idx = t + GEMM_THREADS * s;
       if (!AKC) {
         const int kk = idx >> 6, m2 = idx & 63;
-        ra[s] = *(const d2*)(A + 2 * m2 + (int64_t)(k0 + kk) * lda);
+        ra[s] = *(const d2*)(A + 2 * m2 + (int64_t)kk * lda);
       } else {
         const int m = idx >> 3, kp = idx & 7;
-        ra[s] = *(const d2*)(A + (k0 + 2 * kp) + (int64_t)m * lda);
+        ra[s] = *(const d2*)(A + 2 * kp + (int64_t)m * lda);
       }
       if (!BKC) {
         const int kk = idx >> 6, n2 = idx & 63;
-        rb[s] = *(const d2*)(B + 2 * n2 + (int64_t)(k0 + kk) * ldb);
+        rb[s] = *(const d2*)(B + 2 * n2 + (int64_t)kk * ldb);
       } else {
         const int n = idx >> 3, kp = idx & 7;
-        rb[s] = *(const d2*)(B + (k0 + 2 * kp) + (int64_t)n * ldb);
+        rb[s] = *(const d2*)(B + 2 * kp + (int64_t)n * ldb);
       }
     }
   };
@@ -134,6 +138,16 @@ __device__ __forceinline__ void gemm_blk(const double* __restrict__ A, int64_t l
     if (st + 1 < nst) sstore(cur ^ 1);
     __syncthreads();
   }
+}
+
+// gemm_core over one contiguous operand pair:
+//   Aop(m, k) = A[m + k lda] (AKC = false) or A[k + m lda] (AKC = true), same for B.
+template <bool AKC, bool BKC>
+__device__ __forceinline__ void gemm_blk(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+                                         int64_t ldb, int K, v4d (&acc)[4][4], double* sm) {
+  auto ap = [=](int k0) { return AKC ? A + k0 : A + (int64_t)k0 * lda; };
+  auto bp = [=](int k0) { return BKC ? B + k0 : B + (int64_t)k0 * ldb; };
+  gemm_core<AKC, BKC>(ap, lda, bp, ldb, K, acc, sm);
 }
 
 __device__ __forceinline__ void acc_zero(v4d (&acc)[4][4]) {

@@ -27,7 +27,7 @@ struct Plan {
   bool grad = false;
   size_t off_tiles = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
-         off_info = 0, off_tmp = 0;
+         off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0;
   size_t bytes = 0;
 };
 
@@ -51,7 +51,8 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad) {
   };
   const size_t tt = (size_t)ts * ts;
   p.off_tiles = take((size_t)(p.NT * (p.NT + 1) / 2) * tt * 8);
-  p.off_xd = p.grad ? take((size_t)p.NT * tt * 8) : 0;
+  p.off_xd = take((size_t)p.NT * tt * 8);
+  p.off_ptmp = p.grad ? take((size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8) : 0;
   p.off_dinv = take((size_t)p.NT * p.T * BLKH * BLKH * 8);
   p.off_ld = take((size_t)p.NT * p.T * 8);
   p.off_xs = take((size_t)p.npad * 8);
@@ -60,6 +61,8 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad) {
   p.off_yv = take((size_t)p.npad * 8);
   p.off_av = take((size_t)p.npad * 8);
   p.off_tmp = take((size_t)p.npad * 8);
+  p.off_y = take((size_t)p.npad * 8);
+  p.off_alpha = take((size_t)p.npad * 8);
   p.off_perm = take((size_t)p.npad * 4);
   p.off_keys = take((size_t)p.P * 8);
   p.off_box = take(8 * 8);
@@ -216,11 +219,16 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
   return EXAGEO_OK;
 }
 
+// y = L^-1 z with the explicit inverses of the diagonal tiles, then eq. (2).
 exageo_status solve_reduce(exageo_ctx* c, const Plan& p) {
-  double* yv = at<double>(c, p.off_yv);
-  exg::launch_copy(yv, at<double>(c, p.off_zs), p.npad, c->stream);
-  exg::launch_trsv_fwd(at<double>(c, p.off_tiles), p.ts, p.NT, p.n, at<double>(c, p.off_dinv), yv, c->stream);
-  exg::launch_finalize_loglik(yv, p.n, at<double>(c, p.off_ld), p.NT * p.T, at<double>(c, p.off_out), c->stream);
+  double* rhs = at<double>(c, p.off_yv);
+  double* y = at<double>(c, p.off_y);
+  double* tiles = at<double>(c, p.off_tiles);
+  double* Xd = at<double>(c, p.off_xd);
+  exg::launch_diag_inverses(Xd, tiles, at<double>(c, p.off_dinv), p.ts, p.NT, c->stream);
+  exg::launch_copy(rhs, at<double>(c, p.off_zs), p.npad, c->stream);
+  exg::launch_trsv_fwd(tiles, Xd, p.ts, p.NT, p.n, rhs, y, c->stream);
+  exg::launch_finalize_loglik(y, p.n, at<double>(c, p.off_ld), p.NT * p.T, at<double>(c, p.off_out), c->stream);
   HIPCHK(c, hipGetLastError());
   rec(c, 4);
   return EXAGEO_OK;
@@ -228,13 +236,15 @@ exageo_status solve_reduce(exageo_ctx* c, const Plan& p) {
 
 exageo_status gradient(exageo_ctx* c, const Plan& p) {
   double* tiles = at<double>(c, p.off_tiles);
-  double* av = at<double>(c, p.off_av);
-  exg::launch_copy(av, at<double>(c, p.off_yv), p.npad, c->stream);
-  exg::launch_trsv_bwd(tiles, p.ts, p.NT, at<double>(c, p.off_dinv), av, c->stream);
+  double* rhs = at<double>(c, p.off_av);
+  double* av = at<double>(c, p.off_alpha);
   double* Xd = at<double>(c, p.off_xd);
-  exg::launch_diag_inverses(Xd, tiles, at<double>(c, p.off_dinv), p.ts, p.NT, c->stream);
+  // a = Sigma^-1 z = L^-T y
+  exg::launch_copy(rhs, at<double>(c, p.off_y), p.npad, c->stream);
+  exg::launch_trsv_bwd(tiles, Xd, p.ts, p.NT, rhs, av, c->stream);
+  // L^-1 in place, then the fused LAUUM + contraction
   for (int64_t k = 0; k < p.NT; ++k)
-    exg::launch_trtri_step(tiles, Xd + k * p.ts * p.ts, p.ts, p.NT, k, p.n, c->stream);
+    exg::launch_trtri_step(tiles, Xd + k * p.ts * p.ts, at<double>(c, p.off_ptmp), p.ts, p.NT, k, p.n, c->stream);
   exg::launch_lauum_contract(tiles, p.ts, p.NT, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
                              at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part), c->stream);
   exg::launch_finalize_grad(at<double>(c, p.off_part), exg::lauum_blocks(p.ts, p.NT), at<double>(c, p.off_out) + 3,
@@ -543,7 +553,11 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
     return s == EXAGEO_ENOTPD;
   };
   double th0[3];
-  for (int k = 0; k < 3; ++k) th0[k] = theta0 ? theta0[k] : lb[k];
+  // default start: the lower bound for the derivative-free search (the
+  // paper's convention); the geometric centre of the box for the gradient
+  // method, whose first step would otherwise sit on the flat face beta -> 0
+  for (int k = 0; k < 3; ++k)
+    th0[k] = theta0 ? theta0[k] : (method == EXAGEO_DFO ? lb[k] : std::sqrt(lb[k] * ub[k]));
   exg::MleResult res = method == EXAGEO_DFO ? exg::maximize_dfo(obj, lb, ub, th0, tol, max_iters)
                                             : exg::maximize_lbfgsb(obj, lb, ub, th0, tol, max_iters);
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

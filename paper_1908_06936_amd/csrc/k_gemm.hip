@@ -127,28 +127,30 @@ __global__ __launch_bounds__(256, 2) void k_dinv_left(double* __restrict__ Xd, c
 }
 
 // --------------------------------------------------------- tile TRTRI step k
-// A_ik <- -A_ik X_kk, i > k: one 128-row strip per workgroup, output column
-// blocks in ascending order (column block c reads columns >= c only).
-__global__ __launch_bounds__(256, 2) void k_tri_right(double* __restrict__ tiles, const double* __restrict__ Xk,
-                                                      int64_t ts, int T, int64_t k, int64_t g0) {
+// P_i = -A_ik X_kk for i > k, into the buffer P (tile i - k - 1); one block
+// (u, v) per workgroup, k range restricted to the non-zero rows v*128.. of the
+// lower-triangular X_kk.
+__global__ __launch_bounds__(256, 2) void k_tri_right(const double* __restrict__ tiles, const double* __restrict__ Xk,
+                                                      double* __restrict__ P, int64_t ts, int T, int64_t k,
+                                                      int64_t nreal) {
   __shared__ double sm[GEMM_LDS];
-  const int64_t g = g0 + blockIdx.x;
-  const int64_t i = g / T;
-  const int u = (int)(g % T);
-  double* S = tile_ptr(tiles, i, k, ts) + u * BLK;
-  for (int c = 0; c < T; ++c) {
-    v4d acc[4][4];
-    acc_zero(acc);
-    const int64_t off = (int64_t)c * BLK * ts;
-    gemm_blk<false, true>(S + off, ts, Xk + c * BLK + off, ts, (int)(ts - c * BLK), acc, sm);
-    acc_store(S + off, ts, acc, -1.0, false);
-    __syncthreads();
-  }
+  const int64_t b = blockIdx.x;
+  const int64_t i = k + 1 + b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  const int64_t off = (int64_t)v * BLK * ts;
+  const double* A = tile_ptr((double*)tiles, i, k, ts) + u * BLK + off;
+  double* C = P + (i - k - 1) * ts * ts + u * BLK + off;
+  v4d acc[4][4];
+  acc_zero(acc);
+  // padded rows of L^-1 are zero: store zeros (the buffer is copied back whole)
+  if (i * ts + u * BLK < nreal) gemm_blk<false, true>(A, ts, Xk + v * BLK + off, ts, (int)(ts - v * BLK), acc, sm);
+  acc_store(C, ts, acc, -1.0, false);
 }
 
-// A_ij += A_ik A_kj for k < i < NT, 0 <= j < k
-__global__ __launch_bounds__(256, 2) void k_tri_gemm(double* __restrict__ tiles, int64_t ts, int T, int64_t k,
-                                                     int64_t nreal) {
+// A_ij += P_i A_kj for k < i < NT, 0 <= j < k (P_i = the new A_ik)
+__global__ __launch_bounds__(256, 2) void k_tri_gemm(double* __restrict__ tiles, const double* __restrict__ P,
+                                                     int64_t ts, int T, int64_t k, int64_t nreal) {
   __shared__ double sm[GEMM_LDS];
   const int64_t b = blockIdx.x;
   const int64_t p = b / (T * T);
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(256, 2) void k_tri_gemm(double* __restrict__ tiles,
   const int u = sub / T, v = sub % T;
   const int64_t i = k + 1 + p / k, j = p % k;
   if (i * ts + u * BLK >= nreal) return;
-  const double* A = tile_ptr(tiles, i, k, ts) + u * BLK;
+  const double* A = P + (i - k - 1) * ts * ts + u * BLK;
   const double* B = tile_ptr(tiles, k, j, ts) + (int64_t)v * BLK * ts;
   double* C = tile_ptr(tiles, i, j, ts) + u * BLK + (int64_t)v * BLK * ts;
   v4d acc[4][4];
@@ -165,21 +167,33 @@ __global__ __launch_bounds__(256, 2) void k_tri_gemm(double* __restrict__ tiles,
   acc_store(C, ts, acc, 1.0, true);
 }
 
-// A_kj <- X_kk A_kj, j < k: one 128-column strip per workgroup, output row
-// blocks in descending order (row block r reads rows <= r only).
-__global__ __launch_bounds__(256, 2) void k_tri_left(double* __restrict__ tiles, const double* __restrict__ Xk,
-                                                     int64_t ts, int T, int64_t k) {
+// R_j = X_kk A_kj for j < k, into the buffer P (tile j); k range restricted
+// to the non-zero columns ..(u+1)*128 of row block u of X_kk.
+__global__ __launch_bounds__(256, 2) void k_tri_left(const double* __restrict__ tiles, const double* __restrict__ Xk,
+                                                     double* __restrict__ P, int64_t ts, int T, int64_t k) {
   __shared__ double sm[GEMM_LDS];
-  const int64_t j = blockIdx.x / T;
-  const int v = (int)(blockIdx.x % T);
-  double* S = tile_ptr(tiles, k, j, ts) + (int64_t)v * BLK * ts;
-  for (int r = T - 1; r >= 0; --r) {
-    v4d acc[4][4];
-    acc_zero(acc);
-    gemm_blk<false, true>(Xk + r * BLK, ts, S, ts, (r + 1) * BLK, acc, sm);
-    acc_store(S + r * BLK, ts, acc, 1.0, false);
-    __syncthreads();
-  }
+  const int64_t b = blockIdx.x;
+  const int64_t j = b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  const int64_t off = (int64_t)v * BLK * ts;
+  const double* B = tile_ptr((double*)tiles, k, j, ts) + off;
+  double* C = P + j * ts * ts + u * BLK + off;
+  v4d acc[4][4];
+  acc_zero(acc);
+  gemm_blk<false, true>(Xk + u * BLK, ts, B, ts, (u + 1) * BLK, acc, sm);
+  acc_store(C, ts, acc, 1.0, false);
+}
+
+// tile (i0 + q, jcol) or (irow, j0 + q) <- P tile q, q < count (column or row run)
+__global__ void k_copy_back(double* __restrict__ tiles, const double* __restrict__ P, int64_t ts, int64_t count,
+                            int64_t i0, int64_t j0, int column) {
+  const int64_t tt = ts * ts;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count * tt) return;
+  const int64_t q = e / tt, o = e % tt;
+  const int64_t i = column ? i0 + q : i0, j = column ? j0 : j0 + q;
+  tiles[(tri(i) + j) * tt + o] = P[e];
 }
 
 // ------------------------------------------ fused LAUUM + score contraction
@@ -205,43 +219,52 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract(const double* __restr
   }
   v4d acc[4][4];
   acc_zero(acc);
-  {
-    // K = I: X_II is lower triangular, rows below u*128 only
-    const double* XI = tile_ptr((double*)X, I, I, ts);
-    const double* XJ = tile_ptr((double*)X, I, J, ts);
-    const int64_t r0 = (int64_t)u * BLK;
-    gemm_blk<true, true>(XI + r0 + r0 * ts, ts, XJ + r0 + (int64_t)v * BLK * ts, ts, (int)(ts - r0), acc, sm);
-  }
-  for (int64_t K = I + 1; K < NT; ++K) {
-    if (K * ts >= nreal) break;  // padded rows of X are zero
-    const double* XI = tile_ptr((double*)X, K, I, ts);
-    const double* XJ = tile_ptr((double*)X, K, J, ts);
-    gemm_blk<true, true>(XI + (int64_t)u * BLK * ts, ts, XJ + (int64_t)v * BLK * ts, ts, (int)ts, acc, sm);
-  }
+  // One virtual k range over the tiles K = I, ..., NT-1 of tile columns I and
+  // J: first rows r0.. of tile row I (X_II is lower triangular, so rows above
+  // u*128 of its column block u are zero), then every row of the tiles below.
+  const int64_t r0 = (int64_t)u * BLK, c0 = (int64_t)v * BLK;
+  const int64_t L0 = ts - r0;
+  double* Xm = (double*)X;
+  auto ap = [=](int k0) -> const double* {
+    if (k0 < L0) return tile_ptr(Xm, I, I, ts) + r0 + k0 + r0 * ts;
+    const int64_t kk = k0 - L0, K = I + 1 + kk / ts;
+    return tile_ptr(Xm, K, I, ts) + (kk % ts) + r0 * ts;
+  };
+  auto bp = [=](int k0) -> const double* {
+    if (k0 < L0) return tile_ptr(Xm, I, J, ts) + r0 + k0 + c0 * ts;
+    const int64_t kk = k0 - L0, K = I + 1 + kk / ts;
+    return tile_ptr(Xm, K, J, ts) + (kk % ts) + c0 * ts;
+  };
+  gemm_core<true, true>(ap, ts, bp, ts, (int)(L0 + (NT - 1 - I) * ts), acc, sm);
   // epilogue: regenerate dSigma for this block's entries and contract
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
   double g3[3] = {0.0, 0.0, 0.0};
+  // The 16 values of one row group go through thread-private LDS slots so
+  // that the quadrature loop below indexes them at run time without forcing
+  // the accumulator array out of registers.
+  double* fb = sm;  // 16 x 256 doubles, free after the k loop
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) fb[(j * 4 + r) * GEMM_THREADS + t] = acc[i][j][r];
     const int64_t gi = I * ts + u * BLK + wr * 64 + 16 * i + (lane & 15);
     if (gi >= nreal) continue;
     const double xi = xs[gi], yi = ys[gi], ai = av[gi];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gj = J * ts + v * BLK + wc * 64 + 16 * j + 4 * r + (lane >> 4);
-        if (gj >= nreal || gj > gi) continue;
-        const double wgt = (gi == gj) ? 0.5 : 1.0;  // (w / 2) with w = 1 or 2
-        const double f = wgt * (ai * av[gj] - acc[i][j][r]);
-        const double dx = xi - xs[gj], dy = yi - ys[gj];
-        double d0, d1, d2;
-        matern_grad(sqrt(dx * dx + dy * dy), cst, qt, &d0, &d1, &d2);
-        g3[0] += f * d0;
-        g3[1] += f * d1;
-        g3[2] += f * d2;
-      }
+    for (int e = 0; e < 16; ++e) {
+      const int j = e >> 2, r = e & 3;
+      const int64_t gj = J * ts + v * BLK + wc * 64 + 16 * j + 4 * r + (lane >> 4);
+      if (gj >= nreal || gj > gi) continue;
+      const double wgt = (gi == gj) ? 0.5 : 1.0;  // (w / 2) with w = 1 or 2
+      const double f = wgt * (ai * av[gj] - fb[e * GEMM_THREADS + t]);
+      const double dx = xi - xs[gj], dy = yi - ys[gj];
+      double d0, d1, d2;
+      matern_grad(sqrt(dx * dx + dy * dy), cst, qt, &d0, &d1, &d2);
+      g3[0] += f * d0;
+      g3[1] += f * d1;
+      g3[2] += f * d2;
     }
   }
   __syncthreads();
@@ -291,16 +314,24 @@ void launch_diag_inverses(double* Xd, const double* tiles, const double* dinv, i
   }
 }
 
-void launch_trtri_step(double* tiles, const double* Xk, int64_t ts, int64_t NT, int64_t k, int64_t nreal,
+void launch_trtri_step(double* tiles, const double* Xk, double* P, int64_t ts, int64_t NT, int64_t k, int64_t nreal,
                        hipStream_t s) {
   const int T = (int)(ts / BLK);
-  const int64_t gmax = (nreal + BLK - 1) / BLK;
-  const int64_t g0 = (k + 1) * T;
-  if (gmax > g0) hipLaunchKernelGGL(k_tri_right, dim3((unsigned)(gmax - g0)), dim3(256), 0, s, tiles, Xk, ts, T, k, g0);
-  if (k > 0 && NT - k - 1 > 0)
-    hipLaunchKernelGGL(k_tri_gemm, dim3((unsigned)((NT - k - 1) * k * T * T)), dim3(256), 0, s, tiles, ts, T, k,
-                       nreal);
-  if (k > 0) hipLaunchKernelGGL(k_tri_left, dim3((unsigned)(k * T)), dim3(256), 0, s, tiles, Xk, ts, T, k);
+  const int64_t tt = ts * ts;
+  const int64_t nbelow = NT - k - 1;
+  if (nbelow > 0) {
+    hipLaunchKernelGGL(k_tri_right, dim3((unsigned)(nbelow * T * T)), dim3(256), 0, s, tiles, Xk, P, ts, T, k, nreal);
+    if (k > 0)
+      hipLaunchKernelGGL(k_tri_gemm, dim3((unsigned)(nbelow * k * T * T)), dim3(256), 0, s, tiles, P, ts, T, k,
+                         nreal);
+    hipLaunchKernelGGL(k_copy_back, dim3((unsigned)((nbelow * tt + 255) / 256)), dim3(256), 0, s, tiles, P, ts,
+                       nbelow, k + 1, k, 1);
+  }
+  if (k > 0) {
+    hipLaunchKernelGGL(k_tri_left, dim3((unsigned)(k * T * T)), dim3(256), 0, s, tiles, Xk, P, ts, T, k);
+    hipLaunchKernelGGL(k_copy_back, dim3((unsigned)((k * tt + 255) / 256)), dim3(256), 0, s, tiles, P, ts, k, k,
+                       (int64_t)0, 0);
+  }
   launch_put_diag_tile(tiles, Xk, ts, k, s);
 }
 

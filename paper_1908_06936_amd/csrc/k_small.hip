@@ -144,75 +144,137 @@ __global__ void k_scatter(const double* __restrict__ v, const int32_t* __restric
 }
 
 // ------------------------------------------------ diagonal 128-block factor
-// Cholesky of one 128 x 128 block and the inverse of its factor, in LDS.
-//   factor (right-looking, one barrier per column): at step j every thread
-//   reads d = S_jj, updates S_cr -= S_jr S_jc / d for j < c <= r, and writes
-//   L_rj = S_jr / sqrt(d) into the free upper slot (column r, row j).
-//   inverse: X = L^-1 by rows, T_ij -= (L_im / L_mm) T_mj for i > m >= j with
-//   unit T_mm, then X_ij = T_ij / L_ii (one barrier per row).
+// Cholesky of one 128 x 128 block and the inverse of its factor.
+// 256 threads; thread (tr, tc) = (t % 16, t / 16) holds the 64 entries
+// (tr + 16 p, tc + 16 q) in registers.
+//   factor (right-looking, one barrier per column): the owners of column j
+//   publish it to LDS, then every thread applies A_rc -= A_rj A_cj / A_jj to
+//   its entries with r, c > j and the owners keep L_rj = A_rj / sqrt(A_jj).
+//   inverse: L goes to LDS; with T = unit lower triangular, rows m = 0..127:
+//   the owners of row m publish it and T_ij -= (L_im / L_mm) T_mj for i > m >= j;
+//   then X = L^-1 has X_ij = T_ij / L_ii.
 // Writes L (zeros above the diagonal) over the block, X to dinv (ld 128), the
 // block's sum of 2 ln L_jj to *ldpart and the first failing global column
 // (1-based) to *info with an atomic minimum.
-__global__ __launch_bounds__(1024) void k_potrf_blk(double* __restrict__ A, int64_t lda, double* __restrict__ dinv,
-                                                    double* __restrict__ ldpart, unsigned long long* __restrict__ info,
-                                                    int64_t col0) {
-  __shared__ double S[BLK * (BLK + 1)];
+__global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64_t lda, double* __restrict__ dinv,
+                                                   double* __restrict__ ldpart, unsigned long long* __restrict__ info,
+                                                   int64_t col0) {
+  __shared__ double Ls[BLK * BLK];  // L, column-major
+  __shared__ double pub[2][BLK];    // published column (factor) / row (inverse)
   __shared__ double dg[BLK];
-  constexpr int P = BLK + 1;
-  const int t = threadIdx.x;
-  for (int e = t; e < BLK * BLK; e += 1024) {
-    const int c = e >> 7, r = e & 127;
-    if (r >= c) S[c * P + r] = A[r + (int64_t)c * lda];
-  }
-  __syncthreads();
-  const int r = t & 127, g = t >> 7;
-  for (int j = 0; j < BLK; ++j) {
-    const double d = S[j * P + j];
-    const double sd = sqrt(d);
-    if (t == 0) {
-      dg[j] = sd;
-      if (!(d > 0.0) || !(d <= DBL_MAX)) atomicMin(info, (unsigned long long)(col0 + j + 1));
+  const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
+  double a[8][8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = tr + 16 * p, c = tc + 16 * q;
+      a[p][q] = (r >= c) ? A[r + (int64_t)c * lda] : 0.0;
     }
-    if (r > j) {
-      const double sjr = S[j * P + r];
-      if (g == 0) S[r * P + j] = sjr / sd;
-      const double f = sjr / d;
-      for (int c = j + 1 + g; c <= r; c += 8) S[c * P + r] -= f * S[j * P + c];
-    }
-    __syncthreads();
-  }
-  // inverse: strictly lower part of S holds T, initialised to 0
-  for (int e = t; e < BLK * BLK; e += 1024) {
-    const int c = e >> 7, rr = e & 127;
-    if (rr > c) S[c * P + rr] = 0.0;
-  }
-  __syncthreads();
-  for (int m = 0; m < BLK - 1; ++m) {
-    if (r > m) {
-      const double lim = S[r * P + m] / dg[m];
-      for (int j = g; j <= m; j += 8) {
-        const double tmj = (j == m) ? 1.0 : S[j * P + m];
-        S[j * P + r] -= lim * tmj;
+  // j = 16 qj + jj: the block index qj is a compile-time constant in each
+  // unrolled copy, so the owners address their registers statically
+#pragma unroll
+  for (int qj = 0; qj < 8; ++qj) {
+#pragma unroll 1
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * qj + jj;
+      const int buf = j & 1;
+      if (tc == jj) {
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const int r = tr + 16 * p;
+          if (r >= j) pub[buf][r] = a[p][qj];
+        }
+      }
+      __syncthreads();
+      const double d = pub[buf][j];
+      const double sd = sqrt(d);
+      const double isd = 1.0 / sd;
+      if (t == 0) {
+        dg[j] = sd;
+        if (!(d > 0.0) || !(d <= DBL_MAX)) atomicMin(info, (unsigned long long)(col0 + j + 1));
+      }
+      const double id = isd * isd;
+      double lr[8], lc[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int r = tr + 16 * p;
+        lr[p] = (r > j) ? pub[buf][r] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = tc + 16 * q;
+        lc[q] = (c > j) ? pub[buf][c] * id : 0.0;
+      }
+#pragma unroll
+      for (int q = qj; q < 8; ++q) {
+#pragma unroll
+        for (int p = qj; p < 8; ++p) a[p][q] -= lr[p] * lc[q];
+      }
+      if (tc == jj) {
+#pragma unroll
+        for (int p = qj; p < 8; ++p) {
+          const int r = tr + 16 * p;
+          if (r > j) a[p][qj] = pub[buf][r] * isd;
+          else if (r == j) a[p][qj] = sd;
+        }
       }
     }
-    __syncthreads();
   }
-  for (int e = t; e < BLK * BLK; e += 1024) {
-    const int c = e >> 7, rr = e & 127;
-    double lv, xv;
-    if (rr > c) {
-      lv = S[rr * P + c];
-      xv = S[c * P + rr] / dg[rr];
-    } else if (rr == c) {
-      lv = dg[rr];
-      xv = 1.0 / dg[rr];
-    } else {
-      lv = 0.0;
-      xv = 0.0;
+  // L to LDS and to the block (zeros above the diagonal)
+#pragma unroll
+  for (int p = 0; p < 8; ++p)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = tr + 16 * p, c = tc + 16 * q;
+      const double lv = (r >= c) ? a[p][q] : 0.0;
+      Ls[c * BLK + r] = lv;
+      A[r + (int64_t)c * lda] = lv;
+      a[p][q] = 0.0;  // now T, strictly lower part
     }
-    A[rr + (int64_t)c * lda] = lv;
-    dinv[rr + c * BLK] = xv;
+  __syncthreads();
+#pragma unroll
+  for (int pm = 0; pm < 8; ++pm) {
+#pragma unroll 1
+    for (int mm = 0; mm < 16; ++mm) {
+      const int m = 16 * pm + mm;
+      if (m == BLK - 1) break;
+      const int buf = m & 1;
+      if (tr == mm) {
+#pragma unroll
+        for (int q = 0; q <= pm; ++q) {
+          const int c = tc + 16 * q;
+          if (c < m) pub[buf][c] = a[pm][q];
+        }
+        if (tc == 0) pub[buf][m] = 1.0;
+      }
+      __syncthreads();
+      const double inv_lmm = 1.0 / dg[m];
+      double li[8], tm[8];
+#pragma unroll
+      for (int p = pm; p < 8; ++p) {
+        const int r = tr + 16 * p;
+        li[p] = (r > m) ? Ls[m * BLK + r] * inv_lmm : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q <= pm; ++q) {
+        const int c = tc + 16 * q;
+        tm[q] = (c <= m) ? pub[buf][c] : 0.0;
+      }
+#pragma unroll
+      for (int p = pm; p < 8; ++p)
+#pragma unroll
+        for (int q = 0; q <= pm; ++q) a[p][q] -= li[p] * tm[q];
+    }
   }
+#pragma unroll
+  for (int p = 0; p < 8; ++p)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = tr + 16 * p, c = tc + 16 * q;
+      const double il = 1.0 / dg[r];
+      dinv[r + c * BLK] = (r > c) ? a[p][q] * il : ((r == c) ? il : 0.0);
+    }
   if (t == 0) {
     double s = 0.0;
     for (int j = 0; j < BLK; ++j) s += 2.0 * log(dg[j]);
@@ -221,39 +283,9 @@ __global__ __launch_bounds__(1024) void k_potrf_blk(double* __restrict__ A, int6
 }
 
 // ------------------------------------------------------- triangular solves
-// y_k = L_kk^-1 b_k on one diagonal tile, b_k = yv[k ts .. k ts + ts) on entry.
-// Block c: y_c = Dinv_c b_c, then b_c' -= L_kk[c', c] y_c for c' > c.
-__global__ __launch_bounds__(256) void k_trsv_fwd_diag(const double* __restrict__ Lkk, int64_t ts,
-                                                       const double* __restrict__ dinv, double* __restrict__ yk) {
-  extern __shared__ double sb[];  // ts doubles + 256 scratch
-  double* red = sb + ts;
-  const int t = threadIdx.x, T = (int)(ts / BLK);
-  for (int i = t; i < ts; i += 256) sb[i] = yk[i];
-  __syncthreads();
-  const int r = t & 127, h = t >> 7;
-  for (int c = 0; c < T; ++c) {
-    const double* D = dinv + (int64_t)c * BLK * BLK;
-    double s = 0.0;
-    for (int k = h; k < BLK; k += 2) s += D[r + k * BLK] * sb[c * BLK + k];
-    red[t] = s;
-    __syncthreads();
-    if (h == 0) sb[c * BLK + r] = red[r] + red[r + 128];
-    __syncthreads();
-    // rows below block c inside this tile
-    for (int64_t row = (int64_t)(c + 1) * BLK + t; row < ts; row += 256) {
-      double a = 0.0;
-      const double* Lc = Lkk + row + (int64_t)c * BLK * ts;
-      for (int k = 0; k < BLK; ++k) a += Lc[(int64_t)k * ts] * sb[c * BLK + k];
-      sb[row] -= a;
-    }
-    __syncthreads();
-  }
-  for (int i = t; i < ts; i += 256) yk[i] = sb[i];
-}
-
-// yv_i -= L_ik y_k for the 128-row blocks g0 <= g < g1 below tile k.
+// rhs_i -= L_ik y_k for the 128-row blocks g0 <= g < gmax below tile k.
 __global__ __launch_bounds__(256) void k_gemv_fwd(const double* __restrict__ tiles, int64_t ts, int64_t k,
-                                                  int64_t g0, double* __restrict__ yv) {
+                                                  int64_t g0, const double* __restrict__ yk, double* __restrict__ rhs) {
   extern __shared__ double sy[];  // ts + 256
   double* red = sy + ts;
   const int T = (int)(ts / BLK);
@@ -261,7 +293,7 @@ __global__ __launch_bounds__(256) void k_gemv_fwd(const double* __restrict__ til
   const int64_t i = g / T;
   const int u = (int)(g % T);
   const int t = threadIdx.x;
-  for (int q = t; q < ts; q += 256) sy[q] = yv[k * ts + q];
+  for (int q = t; q < ts; q += 256) sy[q] = yk[q];
   __syncthreads();
   const double* L = tiles + (tri(i) + k) * ts * ts + u * BLK;
   const int r = t & 127, h = t >> 7;
@@ -269,12 +301,47 @@ __global__ __launch_bounds__(256) void k_gemv_fwd(const double* __restrict__ til
   for (int64_t q = h; q < ts; q += 2) s += L[r + q * ts] * sy[q];
   red[t] = s;
   __syncthreads();
-  if (h == 0) yv[i * ts + u * BLK + r] -= red[r] + red[r + 128];
+  if (h == 0) rhs[i * ts + u * BLK + r] -= red[r] + red[r + 128];
+}
+
+// out = X b on one diagonal tile, X lower triangular (explicit inverse);
+// one 128-row block per workgroup
+__global__ __launch_bounds__(256) void k_diag_apply_n(const double* __restrict__ X, int64_t ts,
+                                                      const double* __restrict__ b, double* __restrict__ out) {
+  __shared__ double sb[4096];  // ts <= 4096
+  __shared__ double red[256];
+  const int rb = blockIdx.x, t = threadIdx.x;
+  const int64_t cmax = (int64_t)(rb + 1) * BLK;  // X(row, c) = 0 for c >= cmax
+  for (int64_t q = t; q < cmax; q += 256) sb[q] = b[q];
+  __syncthreads();
+  const int r = t & 127, h = t >> 7;
+  const double* Xr = X + rb * BLK + r;
+  double s = 0.0;
+  for (int64_t c = h; c < cmax; c += 2) s += Xr[c * ts] * sb[c];
+  red[t] = s;
+  __syncthreads();
+  if (h == 0) out[rb * BLK + r] = red[r] + red[r + 128];
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// out = X^T b on one diagonal tile, X lower triangular; one 128-column block
+// per workgroup, one wave per column (lanes run down the column)
+__global__ __launch_bounds__(256) void k_diag_apply_t(const double* __restrict__ X, int64_t ts,
+                                                      const double* __restrict__ b, double* __restrict__ out) {
+  const int cb = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int n = w; n < BLK; n += 4) {
+    const int64_t col = (int64_t)cb * BLK + n;
+    const double* Xc = X + col * ts;
+    double s = 0.0;
+    for (int64_t r = col + lane; r < ts; r += 64) s += Xc[r] * b[r];
+    s = wave_sum(s);
+    if (lane == 0) out[col] = s;
+  }
 }
 
 // rhs_j -= L_kj^T a_k for the 128-column blocks c0 <= c < c1 (columns of tiles j < k).
@@ -295,46 +362,6 @@ __global__ __launch_bounds__(256) void k_gemv_bwd(const double* __restrict__ til
     if (lane == 0) rhs[j * ts + col] -= s;
   }
 }
-
-// a_k = L_kk^-T b_k on one diagonal tile, b_k = rhs[k ts ..) on entry, result in place.
-// Block c descending: a_c = Dinv_c^T b_c, then b_c' -= L_kk[c, c']^T a_c for c' < c.
-__global__ __launch_bounds__(256) void k_trsv_bwd_diag(const double* __restrict__ Lkk, int64_t ts,
-                                                       const double* __restrict__ dinv, double* __restrict__ bk) {
-  extern __shared__ double sb[];  // ts
-  const int t = threadIdx.x, T = (int)(ts / BLK);
-  const int lane = t & 63, w = t >> 6;
-  for (int i = t; i < ts; i += 256) sb[i] = bk[i];
-  __syncthreads();
-  for (int c = T - 1; c >= 0; --c) {
-    const double* D = dinv + (int64_t)c * BLK * BLK;
-    // a_c[n] = sum_k D[k, n] b_c[k]: column n of D
-    double outv[BLK / 4];
-#pragma unroll
-    for (int q = 0; q < BLK / 4; ++q) {
-      const int n = w + 4 * q;
-      double s = 0.0;
-      for (int kk = lane; kk < BLK; kk += 64) s += D[kk + n * BLK] * sb[c * BLK + kk];
-      outv[q] = wave_sum(s);
-    }
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < BLK / 4; ++q) sb[c * BLK + w + 4 * q] = outv[q];
-    }
-    __syncthreads();
-    // b_c'[n] -= sum_r L(c*128 + r, c'*128 + n) a_c[r] for columns before block c
-    for (int64_t col = w; col < (int64_t)c * BLK; col += 4) {
-      const double* Lc = Lkk + (int64_t)c * BLK + col * ts;
-      double s = 0.0;
-      for (int rr = lane; rr < BLK; rr += 64) s += Lc[rr] * sb[c * BLK + rr];
-      s = wave_sum(s);
-      if (lane == 0) sb[col] -= s;
-    }
-    __syncthreads();
-  }
-  for (int i = t; i < ts; i += 256) bk[i] = sb[i];
-}
-
 
 // w = L e on the lower tiles (diagonal tiles read below their diagonal only);
 // one 128-row block per workgroup
@@ -460,30 +487,29 @@ void launch_scatter(const double* v, const int32_t* perm, int64_t n, double* out
 
 void launch_potrf_blk(double* A, int64_t lda, double* dinv, double* ldpart, unsigned long long* info, int64_t col0,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_potrf_blk, dim3(1), dim3(1024), 0, s, A, lda, dinv, ldpart, info, col0);
+  hipLaunchKernelGGL(k_potrf_blk, dim3(1), dim3(256), 0, s, A, lda, dinv, ldpart, info, col0);
 }
 
-void launch_trsv_fwd(const double* tiles, int64_t ts, int64_t NT, int64_t nreal, const double* dinv, double* yv,
-                     hipStream_t s) {
+void launch_trsv_fwd(const double* tiles, const double* Xd, int64_t ts, int64_t NT, int64_t nreal, double* rhs,
+                     double* y, hipStream_t s) {
   const int T = (int)(ts / BLK);
   const size_t shm = (size_t)(ts + 256) * sizeof(double);
   const int64_t gmax = (nreal + BLK - 1) / BLK;  // row blocks holding real rows
   for (int64_t k = 0; k < NT; ++k) {
-    const double* Lkk = tiles + (k * (k + 1) / 2 + k) * ts * ts;
-    hipLaunchKernelGGL(k_trsv_fwd_diag, dim3(1), dim3(256), shm, s, Lkk, ts, dinv + k * T * BLK * BLK, yv + k * ts);
+    hipLaunchKernelGGL(k_diag_apply_n, dim3(T), dim3(256), 0, s, Xd + k * ts * ts, ts, rhs + k * ts, y + k * ts);
     const int64_t g0 = (k + 1) * T;
     if (gmax > g0)
-      hipLaunchKernelGGL(k_gemv_fwd, dim3((unsigned)(gmax - g0)), dim3(256), shm, s, tiles, ts, k, g0, yv);
+      hipLaunchKernelGGL(k_gemv_fwd, dim3((unsigned)(gmax - g0)), dim3(256), shm, s, tiles, ts, k, g0, y + k * ts,
+                         rhs);
   }
 }
 
-void launch_trsv_bwd(const double* tiles, int64_t ts, int64_t NT, const double* dinv, double* av, hipStream_t s) {
+void launch_trsv_bwd(const double* tiles, const double* Xd, int64_t ts, int64_t NT, double* rhs, double* a,
+                     hipStream_t s) {
   const int T = (int)(ts / BLK);
-  const size_t shm = (size_t)ts * sizeof(double);
   for (int64_t k = NT - 1; k >= 0; --k) {
-    const double* Lkk = tiles + (k * (k + 1) / 2 + k) * ts * ts;
-    hipLaunchKernelGGL(k_trsv_bwd_diag, dim3(1), dim3(256), shm, s, Lkk, ts, dinv + k * T * BLK * BLK, av + k * ts);
-    if (k > 0) hipLaunchKernelGGL(k_gemv_bwd, dim3((unsigned)(k * T)), dim3(256), 0, s, tiles, ts, k, av + k * ts, av);
+    hipLaunchKernelGGL(k_diag_apply_t, dim3(T), dim3(256), 0, s, Xd + k * ts * ts, ts, rhs + k * ts, a + k * ts);
+    if (k > 0) hipLaunchKernelGGL(k_gemv_bwd, dim3((unsigned)(k * T)), dim3(256), 0, s, tiles, ts, k, a + k * ts, rhs);
   }
 }
 

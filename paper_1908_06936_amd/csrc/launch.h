@@ -24,9 +24,10 @@ void launch_sort_locations(const double* x, const double* y, const double* z, in
 void launch_scatter(const double* v, const int32_t* perm, int64_t n, double* out, hipStream_t s);
 void launch_potrf_blk(double* A, int64_t lda, double* dinv, double* ldpart, unsigned long long* info, int64_t col0,
                       hipStream_t s);
-void launch_trsv_fwd(const double* tiles, int64_t ts, int64_t NT, int64_t nreal, const double* dinv, double* yv,
+void launch_trsv_fwd(const double* tiles, const double* Xd, int64_t ts, int64_t NT, int64_t nreal, double* rhs,
+                     double* y, hipStream_t s);
+void launch_trsv_bwd(const double* tiles, const double* Xd, int64_t ts, int64_t NT, double* rhs, double* a,
                      hipStream_t s);
-void launch_trsv_bwd(const double* tiles, int64_t ts, int64_t NT, const double* dinv, double* av, hipStream_t s);
 void launch_trmv_lower(const double* tiles, int64_t ts, int64_t NT, int64_t nreal, const double* e, double* w,
                        hipStream_t s);
 void launch_finalize_loglik(const double* yv, int64_t n, const double* ldpart, int64_t nld, double* out,
@@ -44,7 +45,7 @@ void launch_chol_update(double* tiles, int64_t ts, int64_t NT, int64_t k, int64_
 void launch_panel(double* tiles, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k, double* ldpart_k,
                   unsigned long long* info, hipStream_t s);
 void launch_diag_inverses(double* Xd, const double* tiles, const double* dinv, int64_t ts, int64_t NT, hipStream_t s);
-void launch_trtri_step(double* tiles, const double* Xk, int64_t ts, int64_t NT, int64_t k, int64_t nreal,
+void launch_trtri_step(double* tiles, const double* Xk, double* P, int64_t ts, int64_t NT, int64_t k, int64_t nreal,
                        hipStream_t s);
 int64_t lauum_blocks(int64_t ts, int64_t NT);
 void launch_lauum_contract(const double* X, int64_t ts, int64_t NT, int64_t nreal, const double* xs, const double* ys,

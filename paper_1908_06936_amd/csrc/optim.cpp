@@ -58,86 +58,105 @@ MleResult maximize_dfo(const Objective& obj, const double lb[3], const double ub
   };
   auto budget_left = [&]() { return max_evals <= 0 || nev < max_evals; };
 
-  double S[D + 1][D], fv[D + 1];
-  for (int k = 0; k < D; ++k) S[0][k] = std::log(theta0[k]);
-  box.clamp(S[0]);
-  for (int k = 0; k < D; ++k) res.theta[k] = theta0[k];
-  fv[0] = F(S[0]);
-  for (int v = 1; v <= D; ++v) {
-    for (int k = 0; k < D; ++k) S[v][k] = S[0][k];
-    const int k = v - 1;
-    const double width = box.hi[k] - box.lo[k];
-    double step = width > 0 ? std::min(0.5, 0.25 * width) : 0.0;
-    if (S[0][k] + step > box.hi[k]) step = -step;  // step into the box
-    S[v][k] += step;
-    box.clamp(S[v]);
-    fv[v] = budget_left() ? F(S[v]) : std::numeric_limits<double>::infinity();
-  }
   const double alpha = 1.0, gamma = 2.0, rho = 0.5, sigma = 0.5;
   int64_t it = 0;
   bool conv = false;
-  while (!hard && budget_left()) {
-    // order vertices by value (best first)
-    int idx[D + 1] = {0, 1, 2, 3};
-    std::sort(idx, idx + D + 1, [&](int a, int b) { return fv[a] < fv[b]; });
-    double So[D + 1][D], fo[D + 1];
-    for (int v = 0; v <= D; ++v) {
-      fo[v] = fv[idx[v]];
-      for (int k = 0; k < D; ++k) So[v][k] = S[idx[v]][k];
+  double start[D];
+  for (int k = 0; k < D; ++k) start[k] = std::log(theta0[k]);
+  box.clamp(start);
+  for (int k = 0; k < D; ++k) res.theta[k] = theta0[k];
+  // A simplex can collapse onto a flat face of l (e.g. beta so small that
+  // Sigma ~ sigma2 I); each converged run is therefore restarted from its best
+  // vertex with a fresh simplex of half the previous size, until a restart
+  // improves l by less than tol.
+  double frac = 0.25;
+  double prev_best = std::numeric_limits<double>::infinity();
+  for (int restart = 0; restart < 12 && !hard && budget_left(); ++restart, frac *= 0.5) {
+    double S[D + 1][D], fv[D + 1];
+    for (int k = 0; k < D; ++k) S[0][k] = start[k];
+    fv[0] = F(S[0]);
+    for (int v = 1; v <= D; ++v) {
+      for (int k = 0; k < D; ++k) S[v][k] = S[0][k];
+      const int k = v - 1;
+      double step = frac * (box.hi[k] - box.lo[k]);
+      if (S[0][k] + step > box.hi[k]) step = -step;  // step into the box
+      S[v][k] += step;
+      box.clamp(S[v]);
+      fv[v] = budget_left() ? F(S[v]) : std::numeric_limits<double>::infinity();
     }
-    for (int v = 0; v <= D; ++v) {
-      fv[v] = fo[v];
-      for (int k = 0; k < D; ++k) S[v][k] = So[v][k];
+    bool run_conv = false;
+    while (!hard && budget_left()) {
+      // order vertices by value (best first)
+      int idx[D + 1] = {0, 1, 2, 3};
+      std::sort(idx, idx + D + 1, [&](int a, int b) { return fv[a] < fv[b]; });
+      double So[D + 1][D], fo[D + 1];
+      for (int v = 0; v <= D; ++v) {
+        fo[v] = fv[idx[v]];
+        for (int k = 0; k < D; ++k) So[v][k] = S[idx[v]][k];
+      }
+      for (int v = 0; v <= D; ++v) {
+        fv[v] = fo[v];
+        for (int k = 0; k < D; ++k) S[v][k] = So[v][k];
+      }
+      ++it;
+      if (std::isfinite(fv[D]) && std::fabs(fv[D] - fv[0]) < tol) {
+        run_conv = true;
+        break;
+      }
+      double cen[D] = {0, 0, 0};
+      for (int v = 0; v < D; ++v)
+        for (int k = 0; k < D; ++k) cen[k] += S[v][k] / D;
+      double xr[D];
+      for (int k = 0; k < D; ++k) xr[k] = cen[k] + alpha * (cen[k] - S[D][k]);
+      box.clamp(xr);
+      const double fr = F(xr);
+      if (fr < fv[0]) {
+        double xe[D];
+        for (int k = 0; k < D; ++k) xe[k] = cen[k] + gamma * (xr[k] - cen[k]);
+        box.clamp(xe);
+        const double fe = budget_left() ? F(xe) : std::numeric_limits<double>::infinity();
+        if (fe < fr) {
+          for (int k = 0; k < D; ++k) S[D][k] = xe[k];
+          fv[D] = fe;
+        } else {
+          for (int k = 0; k < D; ++k) S[D][k] = xr[k];
+          fv[D] = fr;
+        }
+        continue;
+      }
+      if (fr < fv[D - 1]) {
+        for (int k = 0; k < D; ++k) S[D][k] = xr[k];
+        fv[D] = fr;
+        continue;
+      }
+      // contraction: outside if the reflected point beats the worst, else inside
+      double xc[D];
+      const bool outside = fr < fv[D];
+      for (int k = 0; k < D; ++k)
+        xc[k] = outside ? cen[k] + rho * (xr[k] - cen[k]) : cen[k] + rho * (S[D][k] - cen[k]);
+      box.clamp(xc);
+      if (!budget_left()) break;
+      const double fc = F(xc);
+      if (fc < (outside ? fr : fv[D])) {
+        for (int k = 0; k < D; ++k) S[D][k] = xc[k];
+        fv[D] = fc;
+        continue;
+      }
+      // shrink towards the best vertex
+      for (int v = 1; v <= D && budget_left(); ++v) {
+        for (int k = 0; k < D; ++k) S[v][k] = S[0][k] + sigma * (S[v][k] - S[0][k]);
+        fv[v] = F(S[v]);
+      }
     }
-    ++it;
-    if (std::isfinite(fv[D]) && std::fabs(fv[D] - fv[0]) < tol) {
+    if (!run_conv) break;  // budget or hard failure
+    const double best = -res.f;
+    if (prev_best - best < tol) {
       conv = true;
       break;
     }
-    double cen[D] = {0, 0, 0};
-    for (int v = 0; v < D; ++v)
-      for (int k = 0; k < D; ++k) cen[k] += S[v][k] / D;
-    double xr[D];
-    for (int k = 0; k < D; ++k) xr[k] = cen[k] + alpha * (cen[k] - S[D][k]);
-    box.clamp(xr);
-    const double fr = F(xr);
-    if (fr < fv[0]) {
-      double xe[D];
-      for (int k = 0; k < D; ++k) xe[k] = cen[k] + gamma * (xr[k] - cen[k]);
-      box.clamp(xe);
-      const double fe = budget_left() ? F(xe) : std::numeric_limits<double>::infinity();
-      if (fe < fr) {
-        for (int k = 0; k < D; ++k) S[D][k] = xe[k];
-        fv[D] = fe;
-      } else {
-        for (int k = 0; k < D; ++k) S[D][k] = xr[k];
-        fv[D] = fr;
-      }
-      continue;
-    }
-    if (fr < fv[D - 1]) {
-      for (int k = 0; k < D; ++k) S[D][k] = xr[k];
-      fv[D] = fr;
-      continue;
-    }
-    // contraction: outside if the reflected point beats the worst, else inside
-    double xc[D];
-    const bool outside = fr < fv[D];
-    for (int k = 0; k < D; ++k)
-      xc[k] = outside ? cen[k] + rho * (xr[k] - cen[k]) : cen[k] + rho * (S[D][k] - cen[k]);
-    box.clamp(xc);
-    if (!budget_left()) break;
-    const double fc = F(xc);
-    if (fc < (outside ? fr : fv[D])) {
-      for (int k = 0; k < D; ++k) S[D][k] = xc[k];
-      fv[D] = fc;
-      continue;
-    }
-    // shrink towards the best vertex
-    for (int v = 1; v <= D && budget_left(); ++v) {
-      for (int k = 0; k < D; ++k) S[v][k] = S[0][k] + sigma * (S[v][k] - S[0][k]);
-      fv[v] = F(S[v]);
-    }
+    prev_best = best;
+    for (int k = 0; k < D; ++k) start[k] = std::log(res.theta[k]);
+    box.clamp(start);
   }
   res.iters = it;
   res.evals = nev;
