@@ -26,6 +26,8 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int64_t tri(int64_t i) { return i * (i + 1) / 2; }
 
+
+
 __device__ __forceinline__ double* tile_ptr(double* base, int64_t i, int64_t j, int64_t ts) {
   return base + (tri(i) + j) * ts * ts;
 }
@@ -54,7 +56,7 @@ __device__ __forceinline__ v4d mfma64(double x, double y, v4d c) {
 //     Aop(m, k0 + q) = aptr(k0)[m + q * lda]   (AKC = false, m contiguous)
 //                    = aptr(k0)[q + m * lda]   (AKC = true,  k contiguous)
 //   bptr / Bop(n, k) likewise with ldb, BKC.
-// K must be a multiple of BK; every pair of doubles read must be 16-byte
+// K must be a multiple of 2 BK; every pair of doubles read must be 16-byte
 // aligned.  acc[i][j] holds output rows m = wr*64 + 16 i + (lane & 15) and
 // columns n = wc*64 + 16 j + 4 r + (lane >> 4), r = 0..3 (wr = wave >> 1,
 // wc = wave & 1); with this assignment the lanes of one store instruction
@@ -66,8 +68,9 @@ __device__ __forceinline__ void gemm_core(AP aptr, int64_t lda, BP bptr, int64_t
   const int wr = w >> 1, wc = w & 1;
   double* sA = sm;
   double* sB = sm + 2 * BK * LDP;
-  d2 ra[4], rb[4];
-  auto gload = [&](int k0) {
+  // two register sets: the global loads run two stages ahead of the MFMAs
+  d2 ra0[4], rb0[4], ra1[4], rb1[4];
+  auto gload = [&](int k0, d2 (&ra)[4], d2 (&rb)[4]) {
     const double* A = aptr(k0);
     const double* B = bptr(k0);
 #pragma unroll
@@ -89,7 +92,7 @@ __device__ __forceinline__ void gemm_core(AP aptr, int64_t lda, BP bptr, int64_t
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, d2 (&ra)[4], d2 (&rb)[4]) {
     double* a = sA + buf * BK * LDP;
     double* b = sB + buf * BK * LDP;
 #pragma unroll
@@ -113,13 +116,7 @@ __device__ __forceinline__ void gemm_core(AP aptr, int64_t lda, BP bptr, int64_t
       }
     }
   };
-  const int nst = K / BK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
-    if (st + 1 < nst) gload((st + 1) * BK);
+  auto compute = [&](int cur) {
     const double* a = sA + cur * BK * LDP + wr * 64 + (lane & 15);
     const double* b = sB + cur * BK * LDP + wc * 64 + (lane & 15);
 #pragma unroll
@@ -135,7 +132,22 @@ __device__ __forceinline__ void gemm_core(AP aptr, int64_t lda, BP bptr, int64_t
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(bf[j], af[i], acc[i][j]);
     }
-    if (st + 1 < nst) sstore(cur ^ 1);
+  };
+  const int nst = K / BK;  // even: every K here is a multiple of 128
+  gload(0, ra0, rb0);
+  gload(BK, ra1, rb1);
+  sstore(0, ra0, rb0);
+  __syncthreads();
+  for (int st = 0; st < nst; st += 2) {
+    // stage st from LDS buffer 0; stage st+1 waits in set 1; fetch st+2 into set 0
+    if (st + 2 < nst) gload((st + 2) * BK, ra0, rb0);
+    compute(0);
+    sstore(1, ra1, rb1);
+    __syncthreads();
+    // stage st+1 from LDS buffer 1; stage st+2 waits in set 0; fetch st+3 into set 1
+    if (st + 3 < nst) gload((st + 3) * BK, ra1, rb1);
+    compute(1);
+    if (st + 2 < nst) sstore(0, ra0, rb0);
     __syncthreads();
   }
 }

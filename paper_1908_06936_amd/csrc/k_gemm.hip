@@ -27,9 +27,10 @@ namespace exg {
 // -------------------------------------------------------------- Cholesky
 // trailing update of step k over the tiles (i, j), k < j <= i < NT
 __global__ __launch_bounds__(256, 2) void k_chol_update(double* __restrict__ tiles, int64_t ts, int T, int64_t k,
-                                                        int64_t nreal) {
+                                                        int64_t nreal, int64_t nb) {
   __shared__ double sm[GEMM_LDS];
   const int64_t b = blockIdx.x;
+  if (b >= nb) return;
   const int64_t p = b / (T * T);
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
@@ -132,9 +133,10 @@ __global__ __launch_bounds__(256, 2) void k_dinv_left(double* __restrict__ Xd, c
 // lower-triangular X_kk.
 __global__ __launch_bounds__(256, 2) void k_tri_right(const double* __restrict__ tiles, const double* __restrict__ Xk,
                                                       double* __restrict__ P, int64_t ts, int T, int64_t k,
-                                                      int64_t nreal) {
+                                                      int64_t nreal, int64_t nb) {
   __shared__ double sm[GEMM_LDS];
   const int64_t b = blockIdx.x;
+  if (b >= nb) return;
   const int64_t i = k + 1 + b / (T * T);
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
@@ -150,9 +152,10 @@ __global__ __launch_bounds__(256, 2) void k_tri_right(const double* __restrict__
 
 // A_ij += P_i A_kj for k < i < NT, 0 <= j < k (P_i = the new A_ik)
 __global__ __launch_bounds__(256, 2) void k_tri_gemm(double* __restrict__ tiles, const double* __restrict__ P,
-                                                     int64_t ts, int T, int64_t k, int64_t nreal) {
+                                                     int64_t ts, int T, int64_t k, int64_t nreal, int64_t nb) {
   __shared__ double sm[GEMM_LDS];
   const int64_t b = blockIdx.x;
+  if (b >= nb) return;
   const int64_t p = b / (T * T);
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
@@ -170,9 +173,10 @@ __global__ __launch_bounds__(256, 2) void k_tri_gemm(double* __restrict__ tiles,
 // R_j = X_kk A_kj for j < k, into the buffer P (tile j); k range restricted
 // to the non-zero columns ..(u+1)*128 of row block u of X_kk.
 __global__ __launch_bounds__(256, 2) void k_tri_left(const double* __restrict__ tiles, const double* __restrict__ Xk,
-                                                     double* __restrict__ P, int64_t ts, int T, int64_t k) {
+                                                     double* __restrict__ P, int64_t ts, int T, int64_t k, int64_t nb) {
   __shared__ double sm[GEMM_LDS];
   const int64_t b = blockIdx.x;
+  if (b >= nb) return;
   const int64_t j = b / (T * T);
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
@@ -205,9 +209,11 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract(const double* __restr
                                                            int64_t nreal, const double* __restrict__ xs,
                                                            const double* __restrict__ ys, const double* __restrict__ av,
                                                            const double* __restrict__ qt,
-                                                           const double* __restrict__ cst, double* __restrict__ part) {
+                                                           const double* __restrict__ cst, double* __restrict__ part,
+                                                           int64_t nb) {
   __shared__ double sm[GEMM_LDS];
   const int64_t b = blockIdx.x;
+  if (b >= nb) return;
   const int64_t p = b / (T * T);
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
@@ -282,7 +288,7 @@ void launch_chol_update(double* tiles, int64_t ts, int64_t NT, int64_t k, int64_
   const int64_t m = NT - k - 1;
   if (m <= 0) return;
   const int64_t nblk = m * (m + 1) / 2 * T * T;
-  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, tiles, ts, T, k, nreal);
+  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, tiles, ts, T, k, nreal, nblk);
 }
 
 void launch_panel(double* tiles, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k, double* ldpart_k,
@@ -320,15 +326,16 @@ void launch_trtri_step(double* tiles, const double* Xk, double* P, int64_t ts, i
   const int64_t tt = ts * ts;
   const int64_t nbelow = NT - k - 1;
   if (nbelow > 0) {
-    hipLaunchKernelGGL(k_tri_right, dim3((unsigned)(nbelow * T * T)), dim3(256), 0, s, tiles, Xk, P, ts, T, k, nreal);
+    const int64_t nr = nbelow * T * T, ng = nbelow * k * T * T;
+    hipLaunchKernelGGL(k_tri_right, dim3((unsigned)nr), dim3(256), 0, s, tiles, Xk, P, ts, T, k, nreal, nr);
     if (k > 0)
-      hipLaunchKernelGGL(k_tri_gemm, dim3((unsigned)(nbelow * k * T * T)), dim3(256), 0, s, tiles, P, ts, T, k,
-                         nreal);
+      hipLaunchKernelGGL(k_tri_gemm, dim3((unsigned)ng), dim3(256), 0, s, tiles, P, ts, T, k, nreal, ng);
     hipLaunchKernelGGL(k_copy_back, dim3((unsigned)((nbelow * tt + 255) / 256)), dim3(256), 0, s, tiles, P, ts,
                        nbelow, k + 1, k, 1);
   }
   if (k > 0) {
-    hipLaunchKernelGGL(k_tri_left, dim3((unsigned)(k * T * T)), dim3(256), 0, s, tiles, Xk, P, ts, T, k);
+    const int64_t nl = k * T * T;
+    hipLaunchKernelGGL(k_tri_left, dim3((unsigned)nl), dim3(256), 0, s, tiles, Xk, P, ts, T, k, nl);
     hipLaunchKernelGGL(k_copy_back, dim3((unsigned)((k * tt + 255) / 256)), dim3(256), 0, s, tiles, P, ts, k, k,
                        (int64_t)0, 0);
   }
@@ -343,8 +350,9 @@ int64_t lauum_blocks(int64_t ts, int64_t NT) {
 void launch_lauum_contract(const double* X, int64_t ts, int64_t NT, int64_t nreal, const double* xs, const double* ys,
                            const double* av, const double* qt, const double* cst, double* part, hipStream_t s) {
   const int T = (int)(ts / BLK);
-  hipLaunchKernelGGL(k_lauum_contract, dim3((unsigned)lauum_blocks(ts, NT)), dim3(256), 0, s, X, ts, T, NT, nreal, xs,
-                     ys, av, qt, cst, part);
+  const int64_t nb = lauum_blocks(ts, NT);
+  hipLaunchKernelGGL(k_lauum_contract, dim3((unsigned)nb), dim3(256), 0, s, X, ts, T, NT, nreal, xs, ys, av, qt, cst,
+                     part, nb);
 }
 
 }  // namespace exg
