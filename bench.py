@@ -27,6 +27,25 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the trailing-update kernel from two rocprofv3 --pmc
+# passes over this workload (profiles/k_chol_update_n40000_ts768_counters.md):
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a plain 1 GiB
+# device copy read and write 1 GiB.  Valid only for the kernel sources the
+# counters were taken on (fingerprint below); otherwise reported as null.
+TRAFFIC_BYTES_PER_LAUNCH = (9.942e6 * 2.0 + 2.047e6 * 1.0) * 1024
+TRAFFIC_SOURCES = ("paper_1908_06936_amd/csrc/common.h", "paper_1908_06936_amd/csrc/k_gemm.hip")
+TRAFFIC_FINGERPRINT = "adfbc0efbebe41a9c2ac4a023a422f82d9bbbbe7"
+
+
+def traffic_bytes():
+    import hashlib
+
+    h = hashlib.sha1()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_BYTES_PER_LAUNCH if h.hexdigest() == TRAFFIC_FINGERPRINT else None
+
 
 def cpu_baseline(n_full: int, theta, sample_n: int) -> dict:
     """The oracle (CPU, FP64) on a bounded sample, scaled by n^3 to n_full."""
@@ -55,7 +74,20 @@ def main() -> int:
     ap.add_argument("--ts", type=int, default=768)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=1500)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8}))
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -124,7 +156,8 @@ def main() -> int:
                    "n": n, "ts": ts, "theta": theta},
         "roofline": {"bound": "mfma", "kernel": "k_chol_update (trailing SYRK/GEMM of the tile Cholesky)",
                      "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic_bytes(),
+                     "traffic_unit": "bytes per launch (HBM fetch + write)",
                      "flops_per_launch": upd_flops / max(upd_launch, 1),
                      "avg_launch_ms": upd_ms / max(upd_launch, 1)},
         "potrf_tflops": chol_tflops,
