@@ -28,8 +28,26 @@ __device__ __forceinline__ int64_t tri(int64_t i) { return i * (i + 1) / 2; }
 
 
 
-__device__ __forceinline__ double* tile_ptr(double* base, int64_t i, int64_t j, int64_t ts) {
-  return base + (tri(i) + j) * ts * ts;
+// The tile matrix: the NT diagonal tiles in one FP64 array, the off-diagonal
+// tiles (i > j) in a second array packed by tile columns, so that the tiles
+// below the diagonal of one column are contiguous:
+//   off_index(i, j) = j (NT - 1) - j (j - 1) / 2 + (i - j - 1).
+// Every tile is ts x ts, column-major (leading dimension ts).  In FP64 mode the
+// off-diagonal array holds doubles; in mixed precision it holds 4-byte slots
+// (FP32 values, or BF16 values in the first half of the slot).
+struct TileMat {
+  double* diag;
+  void* off;
+  int64_t ts, NT;
+};
+
+__host__ __device__ __forceinline__ int64_t off_index(int64_t i, int64_t j, int64_t NT) {
+  return j * (NT - 1) - j * (j - 1) / 2 + (i - j - 1);
+}
+
+// FP64 tile (i, j), i >= j, of an all-FP64 tile matrix
+__device__ __forceinline__ double* tptr(const TileMat& M, int64_t i, int64_t j) {
+  return (i == j) ? M.diag + i * M.ts * M.ts : (double*)M.off + off_index(i, j, M.NT) * M.ts * M.ts;
 }
 
 // Decode p in [0, m(m+1)/2) into (a, b), 0 <= b <= a < m, a ascending with p.

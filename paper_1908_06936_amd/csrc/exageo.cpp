@@ -25,7 +25,7 @@ constexpr int NEV = 512;                     // profiling events
 struct Plan {
   int64_t n = 0, ts = 0, NT = 0, T = 0, npad = 0, P = 0;
   bool grad = false;
-  size_t off_tiles = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
+  size_t off_diag = 0, off_offt = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
          off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0;
   size_t bytes = 0;
@@ -50,7 +50,8 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad) {
     return at;
   };
   const size_t tt = (size_t)ts * ts;
-  p.off_tiles = take((size_t)(p.NT * (p.NT + 1) / 2) * tt * 8);
+  p.off_diag = take((size_t)p.NT * tt * 8);
+  p.off_offt = take((size_t)std::max<int64_t>(1, p.NT * (p.NT - 1) / 2) * tt * 8);
   p.off_xd = take((size_t)p.NT * tt * 8);
   p.off_ptmp = p.grad ? take((size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8) : 0;
   p.off_dinv = take((size_t)p.NT * p.T * BLKH * BLKH * 8);
@@ -182,23 +183,39 @@ exageo_status prepare_locations(exageo_ctx* c, const Plan& p, const double* x, c
   return EXAGEO_OK;
 }
 
+exg::TileMat tilemat(exageo_ctx* c, const Plan& p) {
+  exg::TileMat M;
+  M.diag = at<double>(c, p.off_diag);
+  M.off = at<void>(c, p.off_offt);
+  M.ts = p.ts;
+  M.NT = p.NT;
+  return M;
+}
+
+// FP64 tiles (k+1, k), ..., (NT-1, k): contiguous in the column-packed layout
+double* below_fp64(const exg::TileMat& M, int64_t k) {
+  return (double*)M.off + exg::off_index(k + 1, k, M.NT) * M.ts * M.ts;
+}
+
 // Sigma(theta) tiles and their Cholesky factor in place.
 exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
-  double* tiles = at<double>(c, p.off_tiles);
+  const exg::TileMat M = tilemat(c, p);
+  const int64_t tt = p.ts * p.ts;
   exg::launch_quad_table(theta, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   exg::launch_fill_info(at<unsigned long long>(c, p.off_info), c->stream);
-  exg::launch_gen_tiles(tiles, p.ts, p.NT, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys),
-                        at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
+  exg::launch_gen_tiles(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), at<double>(c, p.off_qt),
+                        at<double>(c, p.off_cst), nullptr, c->stream);
   rec(c, 2);
   double upd_flops = 0.0;
   int nupd = 0;
   for (int64_t k = 0; k < p.NT; ++k) {
-    exg::launch_panel(tiles, p.ts, p.NT, k, p.n, at<double>(c, p.off_dinv) + k * p.T * BLKH * BLKH,
+    double* below = (k + 1 < p.NT) ? below_fp64(M, k) : nullptr;
+    exg::launch_panel(M.diag + k * tt, below, p.ts, p.NT, k, p.n, at<double>(c, p.off_dinv) + k * p.T * BLKH * BLKH,
                       at<double>(c, p.off_ld) + k * p.T, at<unsigned long long>(c, p.off_info), c->stream);
     if (k + 1 < p.NT) {
       const int slot = EV_UPD0 + 2 * nupd;
       if (slot + 1 < c->nev_created) rec(c, slot);
-      exg::launch_chol_update(tiles, p.ts, p.NT, k, p.n, c->stream);
+      exg::launch_chol_update(M, below, k, p.n, false, c->stream);
       if (slot + 1 < c->nev_created) rec(c, slot + 1);
       ++nupd;
       // algorithmic flops of this update over the real rows
@@ -223,11 +240,11 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
 exageo_status solve_reduce(exageo_ctx* c, const Plan& p) {
   double* rhs = at<double>(c, p.off_yv);
   double* y = at<double>(c, p.off_y);
-  double* tiles = at<double>(c, p.off_tiles);
+  const exg::TileMat M = tilemat(c, p);
   double* Xd = at<double>(c, p.off_xd);
-  exg::launch_diag_inverses(Xd, tiles, at<double>(c, p.off_dinv), p.ts, p.NT, c->stream);
+  exg::launch_diag_inverses(Xd, M.diag, at<double>(c, p.off_dinv), p.ts, p.NT, c->stream);
   exg::launch_copy(rhs, at<double>(c, p.off_zs), p.npad, c->stream);
-  exg::launch_trsv_fwd(tiles, Xd, p.ts, p.NT, p.n, rhs, y, c->stream);
+  exg::launch_trsv_fwd(M, false, Xd, p.n, rhs, y, c->stream);
   exg::launch_finalize_loglik(y, p.n, at<double>(c, p.off_ld), p.NT * p.T, at<double>(c, p.off_out), c->stream);
   HIPCHK(c, hipGetLastError());
   rec(c, 4);
@@ -235,17 +252,17 @@ exageo_status solve_reduce(exageo_ctx* c, const Plan& p) {
 }
 
 exageo_status gradient(exageo_ctx* c, const Plan& p) {
-  double* tiles = at<double>(c, p.off_tiles);
+  const exg::TileMat M = tilemat(c, p);
   double* rhs = at<double>(c, p.off_av);
   double* av = at<double>(c, p.off_alpha);
   double* Xd = at<double>(c, p.off_xd);
   // a = Sigma^-1 z = L^-T y
   exg::launch_copy(rhs, at<double>(c, p.off_y), p.npad, c->stream);
-  exg::launch_trsv_bwd(tiles, Xd, p.ts, p.NT, rhs, av, c->stream);
+  exg::launch_trsv_bwd(M, false, Xd, rhs, av, c->stream);
   // L^-1 in place, then the fused LAUUM + contraction
   for (int64_t k = 0; k < p.NT; ++k)
-    exg::launch_trtri_step(tiles, Xd + k * p.ts * p.ts, at<double>(c, p.off_ptmp), p.ts, p.NT, k, p.n, c->stream);
-  exg::launch_lauum_contract(tiles, p.ts, p.NT, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
+    exg::launch_trtri_step(M, Xd + k * p.ts * p.ts, at<double>(c, p.off_ptmp), k, p.n, c->stream);
+  exg::launch_lauum_contract(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
                              at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part), c->stream);
   exg::launch_finalize_grad(at<double>(c, p.off_part), exg::lauum_blocks(p.ts, p.NT), at<double>(c, p.off_out) + 3,
                             c->stream);
@@ -494,7 +511,7 @@ exageo_status exageo_simulate(exageo_ctx* c, int64_t n, const double* x, const d
   st = factorize(c, p, theta);
   if (st) return st;
   double* w = at<double>(c, p.off_tmp);
-  exg::launch_trmv_lower(at<double>(c, p.off_tiles), p.ts, p.NT, p.n, at<double>(c, p.off_zs), w, c->stream);
+  exg::launch_trmv_lower(tilemat(c, p), p.n, at<double>(c, p.off_zs), w, c->stream);
   exg::launch_scatter(w, at<int32_t>(c, p.off_perm), p.n, z, c->stream);
   HIPCHK(c, hipGetLastError());
   double out[6], box[5];

@@ -26,22 +26,30 @@ namespace exg {
 
 // -------------------------------------------------------------- Cholesky
 // trailing update of step k over the tiles (i, j), k < j <= i < NT
-__global__ __launch_bounds__(256, 2) void k_chol_update(double* __restrict__ tiles, int64_t ts, int T, int64_t k,
-                                                        int64_t nreal, int64_t nb) {
+// below: the FP64 tiles (k+1, k), ..., (NT-1, k) of column k, contiguous.
+// diag_only: update only the diagonal tiles (j, j) (mixed precision, where the
+// off-diagonal targets are updated by the lower-precision kernels).
+__global__ __launch_bounds__(256, 2) void k_chol_update(TileMat M, const double* __restrict__ below, int T, int64_t k,
+                                                        int64_t nreal, int64_t nb, int diag_only) {
   __shared__ double sm[GEMM_LDS];
+  const int64_t ts = M.ts;
   const int64_t b = blockIdx.x;
   if (b >= nb) return;
   const int64_t p = b / (T * T);
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
   int64_t a, c;
-  tri_decode(p, &a, &c);
+  if (diag_only) {
+    a = c = p;
+  } else {
+    tri_decode(p, &a, &c);
+  }
   const int64_t i = k + 1 + a, j = k + 1 + c;
   if (i == j && u < v) return;
   if (i * ts + u * BLK >= nreal || j * ts + v * BLK >= nreal) return;  // padding: update is zero
-  const double* A = tile_ptr(tiles, i, k, ts) + u * BLK;
-  const double* B = tile_ptr(tiles, j, k, ts) + v * BLK;
-  double* C = tile_ptr(tiles, i, j, ts) + u * BLK + (int64_t)v * BLK * ts;
+  const double* A = below + a * ts * ts + u * BLK;
+  const double* B = below + c * ts * ts + v * BLK;
+  double* C = tptr(M, i, j) + u * BLK + (int64_t)v * BLK * ts;
   v4d acc[4][4];
   acc_zero(acc);
   gemm_blk<false, false>(A, ts, B, ts, (int)ts, acc, sm);
@@ -50,14 +58,20 @@ __global__ __launch_bounds__(256, 2) void k_chol_update(double* __restrict__ til
 
 // panel k, sub-column c: rows g0 + blockIdx.x (128-row blocks, global index)
 //   C = A[g, c] -= A[g, 0:c] A[(k,c), 0:c]^T
-__global__ __launch_bounds__(256, 2) void k_panel_update(double* __restrict__ tiles, int64_t ts, int T, int64_t k,
-                                                         int c, int64_t g0) {
+// The panel of column k is the diagonal tile Dk followed by the contiguous
+// FP64 tiles `below`; row block g (global index) lies in tile i = g / T.
+__device__ __forceinline__ double* panel_tile(double* Dk, double* below, int64_t i, int64_t k, int64_t ts) {
+  return i == k ? Dk : below + (i - k - 1) * ts * ts;
+}
+
+__global__ __launch_bounds__(256, 2) void k_panel_update(double* __restrict__ Dk, double* __restrict__ below,
+                                                         int64_t ts, int T, int64_t k, int c, int64_t g0) {
   __shared__ double sm[GEMM_LDS];
   const int64_t g = g0 + blockIdx.x;
   const int64_t i = g / T;
   const int u = (int)(g % T);
-  double* P = tile_ptr(tiles, i, k, ts) + u * BLK;
-  const double* D = tile_ptr(tiles, k, k, ts) + c * BLK;
+  double* P = panel_tile(Dk, below, i, k, ts) + u * BLK;
+  const double* D = Dk + c * BLK;
   v4d acc[4][4];
   acc_zero(acc);
   gemm_blk<false, false>(P, ts, D, ts, c * BLK, acc, sm);
@@ -66,13 +80,14 @@ __global__ __launch_bounds__(256, 2) void k_panel_update(double* __restrict__ ti
 
 // panel k, sub-column c: C = A[g, c] Dinv_c^T for the blocks below the diagonal
 // block (in place: each workgroup reads only the block it overwrites)
-__global__ __launch_bounds__(256, 2) void k_panel_trsm(double* __restrict__ tiles, int64_t ts, int T, int64_t k, int c,
-                                                       int64_t g0, const double* __restrict__ dinv) {
+__global__ __launch_bounds__(256, 2) void k_panel_trsm(double* __restrict__ Dk, double* __restrict__ below, int64_t ts,
+                                                       int T, int64_t k, int c, int64_t g0,
+                                                       const double* __restrict__ dinv) {
   __shared__ double sm[GEMM_LDS];
   const int64_t g = g0 + blockIdx.x;
   const int64_t i = g / T;
   const int u = (int)(g % T);
-  double* C = tile_ptr(tiles, i, k, ts) + u * BLK + (int64_t)c * BLK * ts;
+  double* C = panel_tile(Dk, below, i, k, ts) + u * BLK + (int64_t)c * BLK * ts;
   v4d acc[4][4];
   acc_zero(acc);
   gemm_blk<false, false>(C, ts, dinv, BLK, BLK, acc, sm);
@@ -131,9 +146,9 @@ __global__ __launch_bounds__(256, 2) void k_dinv_left(double* __restrict__ Xd, c
 // P_i = -A_ik X_kk for i > k, into the buffer P (tile i - k - 1); one block
 // (u, v) per workgroup, k range restricted to the non-zero rows v*128.. of the
 // lower-triangular X_kk.
-__global__ __launch_bounds__(256, 2) void k_tri_right(const double* __restrict__ tiles, const double* __restrict__ Xk,
-                                                      double* __restrict__ P, int64_t ts, int T, int64_t k,
-                                                      int64_t nreal, int64_t nb) {
+__global__ __launch_bounds__(256, 2) void k_tri_right(TileMat M, const double* __restrict__ Xk, double* __restrict__ P,
+                                                      int T, int64_t k, int64_t nreal, int64_t nb) {
+  const int64_t ts = M.ts;
   __shared__ double sm[GEMM_LDS];
   const int64_t b = blockIdx.x;
   if (b >= nb) return;
@@ -141,7 +156,7 @@ __global__ __launch_bounds__(256, 2) void k_tri_right(const double* __restrict__
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
   const int64_t off = (int64_t)v * BLK * ts;
-  const double* A = tile_ptr((double*)tiles, i, k, ts) + u * BLK + off;
+  const double* A = tptr(M, i, k) + u * BLK + off;
   double* C = P + (i - k - 1) * ts * ts + u * BLK + off;
   v4d acc[4][4];
   acc_zero(acc);
@@ -151,8 +166,9 @@ __global__ __launch_bounds__(256, 2) void k_tri_right(const double* __restrict__
 }
 
 // A_ij += P_i A_kj for k < i < NT, 0 <= j < k (P_i = the new A_ik)
-__global__ __launch_bounds__(256, 2) void k_tri_gemm(double* __restrict__ tiles, const double* __restrict__ P,
-                                                     int64_t ts, int T, int64_t k, int64_t nreal, int64_t nb) {
+__global__ __launch_bounds__(256, 2) void k_tri_gemm(TileMat M, const double* __restrict__ P, int T, int64_t k,
+                                                     int64_t nreal, int64_t nb) {
+  const int64_t ts = M.ts;
   __shared__ double sm[GEMM_LDS];
   const int64_t b = blockIdx.x;
   if (b >= nb) return;
@@ -162,8 +178,8 @@ __global__ __launch_bounds__(256, 2) void k_tri_gemm(double* __restrict__ tiles,
   const int64_t i = k + 1 + p / k, j = p % k;
   if (i * ts + u * BLK >= nreal) return;
   const double* A = P + (i - k - 1) * ts * ts + u * BLK;
-  const double* B = tile_ptr(tiles, k, j, ts) + (int64_t)v * BLK * ts;
-  double* C = tile_ptr(tiles, i, j, ts) + u * BLK + (int64_t)v * BLK * ts;
+  const double* B = tptr(M, k, j) + (int64_t)v * BLK * ts;
+  double* C = tptr(M, i, j) + u * BLK + (int64_t)v * BLK * ts;
   v4d acc[4][4];
   acc_zero(acc);
   gemm_blk<false, true>(A, ts, B, ts, (int)ts, acc, sm);
@@ -172,8 +188,9 @@ __global__ __launch_bounds__(256, 2) void k_tri_gemm(double* __restrict__ tiles,
 
 // R_j = X_kk A_kj for j < k, into the buffer P (tile j); k range restricted
 // to the non-zero columns ..(u+1)*128 of row block u of X_kk.
-__global__ __launch_bounds__(256, 2) void k_tri_left(const double* __restrict__ tiles, const double* __restrict__ Xk,
-                                                     double* __restrict__ P, int64_t ts, int T, int64_t k, int64_t nb) {
+__global__ __launch_bounds__(256, 2) void k_tri_left(TileMat M, const double* __restrict__ Xk, double* __restrict__ P,
+                                                     int T, int64_t k, int64_t nb) {
+  const int64_t ts = M.ts;
   __shared__ double sm[GEMM_LDS];
   const int64_t b = blockIdx.x;
   if (b >= nb) return;
@@ -181,7 +198,7 @@ __global__ __launch_bounds__(256, 2) void k_tri_left(const double* __restrict__ 
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
   const int64_t off = (int64_t)v * BLK * ts;
-  const double* B = tile_ptr((double*)tiles, k, j, ts) + off;
+  const double* B = tptr(M, k, j) + off;
   double* C = P + j * ts * ts + u * BLK + off;
   v4d acc[4][4];
   acc_zero(acc);
@@ -190,14 +207,14 @@ __global__ __launch_bounds__(256, 2) void k_tri_left(const double* __restrict__ 
 }
 
 // tile (i0 + q, jcol) or (irow, j0 + q) <- P tile q, q < count (column or row run)
-__global__ void k_copy_back(double* __restrict__ tiles, const double* __restrict__ P, int64_t ts, int64_t count,
-                            int64_t i0, int64_t j0, int column) {
-  const int64_t tt = ts * ts;
+__global__ void k_copy_back(TileMat M, const double* __restrict__ P, int64_t count, int64_t i0, int64_t j0,
+                            int column) {
+  const int64_t tt = M.ts * M.ts;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= count * tt) return;
   const int64_t q = e / tt, o = e % tt;
   const int64_t i = column ? i0 + q : i0, j = column ? j0 : j0 + q;
-  tiles[(tri(i) + j) * tt + o] = P[e];
+  tptr(M, i, j)[o] = P[e];
 }
 
 // ------------------------------------------ fused LAUUM + score contraction
@@ -205,13 +222,14 @@ __global__ void k_copy_back(double* __restrict__ tiles, const double* __restrict
 // followed by g_m += sum (w_ij (a_i a_j - W_ij) / 2) dSigma_m(i, j) over its
 // entries, w = 2 below the diagonal, 1 on it, 0 above and on padding.
 // part[3 b + m] receives the block's sums (zeros for skipped blocks).
-__global__ __launch_bounds__(256, 2) void k_lauum_contract(const double* __restrict__ X, int64_t ts, int T, int64_t NT,
-                                                           int64_t nreal, const double* __restrict__ xs,
+__global__ __launch_bounds__(256, 2) void k_lauum_contract(TileMat M, int T, int64_t nreal,
+                                                           const double* __restrict__ xs,
                                                            const double* __restrict__ ys, const double* __restrict__ av,
                                                            const double* __restrict__ qt,
                                                            const double* __restrict__ cst, double* __restrict__ part,
                                                            int64_t nb) {
   __shared__ double sm[GEMM_LDS];
+  const int64_t ts = M.ts, NT = M.NT;
   const int64_t b = blockIdx.x;
   if (b >= nb) return;
   const int64_t p = b / (T * T);
@@ -230,16 +248,15 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract(const double* __restr
   // u*128 of its column block u are zero), then every row of the tiles below.
   const int64_t r0 = (int64_t)u * BLK, c0 = (int64_t)v * BLK;
   const int64_t L0 = ts - r0;
-  double* Xm = (double*)X;
   auto ap = [=](int k0) -> const double* {
-    if (k0 < L0) return tile_ptr(Xm, I, I, ts) + r0 + k0 + r0 * ts;
+    if (k0 < L0) return tptr(M, I, I) + r0 + k0 + r0 * ts;
     const int64_t kk = k0 - L0, K = I + 1 + kk / ts;
-    return tile_ptr(Xm, K, I, ts) + (kk % ts) + r0 * ts;
+    return tptr(M, K, I) + (kk % ts) + r0 * ts;
   };
   auto bp = [=](int k0) -> const double* {
-    if (k0 < L0) return tile_ptr(Xm, I, J, ts) + r0 + k0 + c0 * ts;
+    if (k0 < L0) return tptr(M, I, J) + r0 + k0 + c0 * ts;
     const int64_t kk = k0 - L0, K = I + 1 + kk / ts;
-    return tile_ptr(Xm, K, J, ts) + (kk % ts) + c0 * ts;
+    return tptr(M, K, J) + (kk % ts) + c0 * ts;
   };
   gemm_core<true, true>(ap, ts, bp, ts, (int)(L0 + (NT - 1 - I) * ts), acc, sm);
   // epilogue: regenerate dSigma for this block's entries and contract
@@ -283,33 +300,36 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract(const double* __restr
 }
 
 // ------------------------------------------------------------- launchers
-void launch_chol_update(double* tiles, int64_t ts, int64_t NT, int64_t k, int64_t nreal, hipStream_t s) {
-  const int T = (int)(ts / BLK);
-  const int64_t m = NT - k - 1;
+void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, bool diag_only,
+                        hipStream_t s) {
+  const int T = (int)(M.ts / BLK);
+  const int64_t m = M.NT - k - 1;
   if (m <= 0) return;
-  const int64_t nblk = m * (m + 1) / 2 * T * T;
-  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, tiles, ts, T, k, nreal, nblk);
+  const int64_t nblk = (diag_only ? m : m * (m + 1) / 2) * T * T;
+  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, M, below, T, k, nreal, nblk,
+                     diag_only ? 1 : 0);
 }
 
-void launch_panel(double* tiles, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k, double* ldpart_k,
-                  unsigned long long* info, hipStream_t s) {
+void launch_panel(double* Dk, double* below, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k,
+                  double* ldpart_k, unsigned long long* info, hipStream_t s) {
   const int T = (int)(ts / BLK);
   const int64_t gmax = (nreal + BLK - 1) / BLK;  // blocks holding real rows
+  (void)NT;
   for (int c = 0; c < T; ++c) {
     const int64_t gd = k * T + c;  // global index of the diagonal block
     if (c > 0 && gmax > gd)
-      hipLaunchKernelGGL(k_panel_update, dim3((unsigned)(gmax - gd)), dim3(256), 0, s, tiles, ts, T, k, c, gd);
-    double* Dblk = tile_ptr_host(tiles, k, k, ts) + c * BLK + (int64_t)c * BLK * ts;
+      hipLaunchKernelGGL(k_panel_update, dim3((unsigned)(gmax - gd)), dim3(256), 0, s, Dk, below, ts, T, k, c, gd);
+    double* Dblk = Dk + c * BLK + (int64_t)c * BLK * ts;
     launch_potrf_blk(Dblk, ts, dinv_k + (int64_t)c * BLK * BLK, ldpart_k + c, info, gd * BLK, s);
     if (gmax > gd + 1)
-      hipLaunchKernelGGL(k_panel_trsm, dim3((unsigned)(gmax - gd - 1)), dim3(256), 0, s, tiles, ts, T, k, c, gd + 1,
-                         dinv_k + (int64_t)c * BLK * BLK);
+      hipLaunchKernelGGL(k_panel_trsm, dim3((unsigned)(gmax - gd - 1)), dim3(256), 0, s, Dk, below, ts, T, k, c,
+                         gd + 1, dinv_k + (int64_t)c * BLK * BLK);
   }
 }
 
-void launch_diag_inverses(double* Xd, const double* tiles, const double* dinv, int64_t ts, int64_t NT, hipStream_t s) {
+void launch_diag_inverses(double* Xd, const double* diag, const double* dinv, int64_t ts, int64_t NT, hipStream_t s) {
   const int T = (int)(ts / BLK);
-  launch_copy_diag_lower(Xd, tiles, ts, NT, s);
+  launch_copy_diag_lower(Xd, diag, ts, NT, s);
   for (int c = 0; c < T; ++c) {
     if (T - 1 - c > 0)
       hipLaunchKernelGGL(k_dinv_right, dim3((unsigned)(NT * (T - 1 - c))), dim3(256), 0, s, Xd, dinv, ts, T, c);
@@ -320,26 +340,25 @@ void launch_diag_inverses(double* Xd, const double* tiles, const double* dinv, i
   }
 }
 
-void launch_trtri_step(double* tiles, const double* Xk, double* P, int64_t ts, int64_t NT, int64_t k, int64_t nreal,
-                       hipStream_t s) {
+void launch_trtri_step(const TileMat& M, const double* Xk, double* P, int64_t k, int64_t nreal, hipStream_t s) {
+  const int64_t ts = M.ts, NT = M.NT;
   const int T = (int)(ts / BLK);
   const int64_t tt = ts * ts;
   const int64_t nbelow = NT - k - 1;
   if (nbelow > 0) {
     const int64_t nr = nbelow * T * T, ng = nbelow * k * T * T;
-    hipLaunchKernelGGL(k_tri_right, dim3((unsigned)nr), dim3(256), 0, s, tiles, Xk, P, ts, T, k, nreal, nr);
-    if (k > 0)
-      hipLaunchKernelGGL(k_tri_gemm, dim3((unsigned)ng), dim3(256), 0, s, tiles, P, ts, T, k, nreal, ng);
-    hipLaunchKernelGGL(k_copy_back, dim3((unsigned)((nbelow * tt + 255) / 256)), dim3(256), 0, s, tiles, P, ts,
-                       nbelow, k + 1, k, 1);
+    hipLaunchKernelGGL(k_tri_right, dim3((unsigned)nr), dim3(256), 0, s, M, Xk, P, T, k, nreal, nr);
+    if (k > 0) hipLaunchKernelGGL(k_tri_gemm, dim3((unsigned)ng), dim3(256), 0, s, M, P, T, k, nreal, ng);
+    hipLaunchKernelGGL(k_copy_back, dim3((unsigned)((nbelow * tt + 255) / 256)), dim3(256), 0, s, M, P, nbelow, k + 1,
+                       k, 1);
   }
   if (k > 0) {
     const int64_t nl = k * T * T;
-    hipLaunchKernelGGL(k_tri_left, dim3((unsigned)nl), dim3(256), 0, s, tiles, Xk, P, ts, T, k, nl);
-    hipLaunchKernelGGL(k_copy_back, dim3((unsigned)((k * tt + 255) / 256)), dim3(256), 0, s, tiles, P, ts, k, k,
-                       (int64_t)0, 0);
+    hipLaunchKernelGGL(k_tri_left, dim3((unsigned)nl), dim3(256), 0, s, M, Xk, P, T, k, nl);
+    hipLaunchKernelGGL(k_copy_back, dim3((unsigned)((k * tt + 255) / 256)), dim3(256), 0, s, M, P, k, k, (int64_t)0,
+                       0);
   }
-  launch_put_diag_tile(tiles, Xk, ts, k, s);
+  launch_copy(M.diag + k * tt, Xk, tt, s);
 }
 
 int64_t lauum_blocks(int64_t ts, int64_t NT) {
@@ -347,12 +366,12 @@ int64_t lauum_blocks(int64_t ts, int64_t NT) {
   return NT * (NT + 1) / 2 * T * T;
 }
 
-void launch_lauum_contract(const double* X, int64_t ts, int64_t NT, int64_t nreal, const double* xs, const double* ys,
-                           const double* av, const double* qt, const double* cst, double* part, hipStream_t s) {
-  const int T = (int)(ts / BLK);
-  const int64_t nb = lauum_blocks(ts, NT);
-  hipLaunchKernelGGL(k_lauum_contract, dim3((unsigned)nb), dim3(256), 0, s, X, ts, T, NT, nreal, xs, ys, av, qt, cst,
-                     part, nb);
+void launch_lauum_contract(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* av,
+                           const double* qt, const double* cst, double* part, hipStream_t s) {
+  const int T = (int)(M.ts / BLK);
+  const int64_t nb = lauum_blocks(M.ts, M.NT);
+  hipLaunchKernelGGL(k_lauum_contract, dim3((unsigned)nb), dim3(256), 0, s, M, T, nreal, xs, ys, av, qt, cst, part,
+                     nb);
 }
 
 }  // namespace exg

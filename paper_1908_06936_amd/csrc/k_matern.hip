@@ -46,13 +46,23 @@ __global__ void k_quad_table(double s2, double beta, double nu, double* __restri
   }
 }
 
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 // Lower tiles of the padded covariance.  One 256-thread block per 128 x 128
 // block (u, v) of tile (I, J); blocks above the diagonal of a diagonal tile
-// are not needed by any later step and are skipped.
-__global__ __launch_bounds__(256) void k_gen_tiles(double* __restrict__ tiles, int64_t ts, int T, int64_t nreal,
-                                                   const double* __restrict__ xs, const double* __restrict__ ys,
-                                                   const double* __restrict__ qt, const double* __restrict__ cst,
+// are not needed by any later step and are skipped.  Mixed precision (tag !=
+// NULL): diagonal tiles FP64, off-diagonal tiles FP32 (tag 0) or BF16 (tag 1),
+// each rounded to nearest even from the FP64 value.
+__global__ __launch_bounds__(256) void k_gen_tiles(TileMat M, int T, int64_t nreal, const double* __restrict__ xs,
+                                                   const double* __restrict__ ys, const double* __restrict__ qt,
+                                                   const double* __restrict__ cst, const uint8_t* __restrict__ tag,
                                                    int64_t tile_first) {
+  const int64_t ts = M.ts;
   const int64_t b = blockIdx.x;
   const int64_t p = tile_first + b / (T * T);
   const int sub = (int)(b % (T * T));
@@ -60,12 +70,23 @@ __global__ __launch_bounds__(256) void k_gen_tiles(double* __restrict__ tiles, i
   int64_t I, J;
   tri_decode(p, &I, &J);
   if (I == J && u < v) return;
-  double* tile = tiles + p * ts * ts;
   const int r = threadIdx.x & 127, c0 = threadIdx.x >> 7;
   const int64_t gi = I * ts + u * BLK + r;
   const bool ipad = gi >= nreal;
   const double xi = ipad ? 0.0 : xs[gi], yi = ipad ? 0.0 : ys[gi];
-  double* out = tile + (u * BLK + r) + (int64_t)(v * BLK) * ts;
+  const int64_t o = (u * BLK + r) + (int64_t)(v * BLK) * ts;  // element offset in the tile
+  // 0: FP64, 1: FP32, 2: BF16
+  const int kind = (!tag || I == J) ? 0 : (tag[off_index(I, J, M.NT)] ? 2 : 1);
+  double* out64 = nullptr;
+  float* out32 = nullptr;
+  uint16_t* out16 = nullptr;
+  if (kind == 0) {
+    out64 = (tag ? (I == J ? M.diag + I * ts * ts : nullptr) : tptr(M, I, J)) + o;
+  } else if (kind == 1) {
+    out32 = (float*)M.off + off_index(I, J, M.NT) * ts * ts + o;
+  } else {
+    out16 = (uint16_t*)((float*)M.off + off_index(I, J, M.NT) * ts * ts) + o;
+  }
   for (int c = c0; c < BLK; c += 2) {
     const int64_t gj = J * ts + v * BLK + c;
     double val;
@@ -75,7 +96,10 @@ __global__ __launch_bounds__(256) void k_gen_tiles(double* __restrict__ tiles, i
       const double dx = xi - xs[gj], dy = yi - ys[gj];
       val = matern_value(sqrt(dx * dx + dy * dy), cst, qt);
     }
-    out[(int64_t)c * ts] = val;
+    const int64_t e = (int64_t)c * ts;
+    if (kind == 0) out64[e] = val;
+    else if (kind == 1) out32[e] = (float)val;
+    else out16[e] = f32_to_bf16_rne((float)val);
   }
 }
 
@@ -96,16 +120,17 @@ void launch_quad_table(const double theta[3], double* qt, double* cst, hipStream
   hipLaunchKernelGGL(k_quad_table, dim3(QNB), dim3(QNK), 0, s, theta[0], theta[1], theta[2], qt, cst);
 }
 
-void launch_gen_tiles(double* tiles, int64_t ts, int64_t NT, int64_t nreal, const double* xs, const double* ys,
-                      const double* qt, const double* cst, hipStream_t s) {
+void launch_gen_tiles(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* qt,
+                      const double* cst, const uint8_t* tag, hipStream_t s) {
+  const int64_t ts = M.ts, NT = M.NT;
   const int T = (int)(ts / BLK);
   const int64_t ntile = NT * (NT + 1) / 2;
   // keep each launch's grid below 2^31 blocks
   const int64_t per = (int64_t)1 << 24;
   for (int64_t f = 0; f < ntile; f += per) {
     const int64_t cnt = (ntile - f < per) ? ntile - f : per;
-    hipLaunchKernelGGL(k_gen_tiles, dim3((unsigned)(cnt * T * T)), dim3(256), 0, s, tiles, ts, T, nreal, xs, ys, qt,
-                       cst, f);
+    hipLaunchKernelGGL(k_gen_tiles, dim3((unsigned)(cnt * T * T)), dim3(256), 0, s, M, T, nreal, xs, ys, qt, cst, tag,
+                       f);
   }
 }
 

@@ -284,8 +284,10 @@ __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64
 
 // ------------------------------------------------------- triangular solves
 // rhs_i -= L_ik y_k for the 128-row blocks g0 <= g < gmax below tile k.
-__global__ __launch_bounds__(256) void k_gemv_fwd(const double* __restrict__ tiles, int64_t ts, int64_t k,
-                                                  int64_t g0, const double* __restrict__ yk, double* __restrict__ rhs) {
+template <typename OT>
+__global__ __launch_bounds__(256) void k_gemv_fwd(TileMat M, int64_t k, int64_t g0, const double* __restrict__ yk,
+                                                  double* __restrict__ rhs) {
+  const int64_t ts = M.ts;
   extern __shared__ double sy[];  // ts + 256
   double* red = sy + ts;
   const int T = (int)(ts / BLK);
@@ -295,10 +297,10 @@ __global__ __launch_bounds__(256) void k_gemv_fwd(const double* __restrict__ til
   const int t = threadIdx.x;
   for (int q = t; q < ts; q += 256) sy[q] = yk[q];
   __syncthreads();
-  const double* L = tiles + (tri(i) + k) * ts * ts + u * BLK;
+  const OT* L = (const OT*)M.off + off_index(i, k, M.NT) * ts * ts + u * BLK;
   const int r = t & 127, h = t >> 7;
   double s = 0.0;
-  for (int64_t q = h; q < ts; q += 2) s += L[r + q * ts] * sy[q];
+  for (int64_t q = h; q < ts; q += 2) s += (double)L[r + q * ts] * sy[q];
   red[t] = s;
   __syncthreads();
   if (h == 0) rhs[i * ts + u * BLK + r] -= red[r] + red[r + 128];
@@ -345,19 +347,21 @@ __global__ __launch_bounds__(256) void k_diag_apply_t(const double* __restrict__
 }
 
 // rhs_j -= L_kj^T a_k for the 128-column blocks c0 <= c < c1 (columns of tiles j < k).
-__global__ __launch_bounds__(256) void k_gemv_bwd(const double* __restrict__ tiles, int64_t ts, int64_t k,
-                                                  const double* __restrict__ ak, double* __restrict__ rhs) {
+template <typename OT>
+__global__ __launch_bounds__(256) void k_gemv_bwd(TileMat M, int64_t k, const double* __restrict__ ak,
+                                                  double* __restrict__ rhs) {
+  const int64_t ts = M.ts;
   const int T = (int)(ts / BLK);
   const int64_t cb = blockIdx.x;  // column block over tiles j < k
   const int64_t j = cb / T;
   const int v = (int)(cb % T);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double* L = tiles + (tri(k) + j) * ts * ts;
+  const OT* L = (const OT*)M.off + off_index(k, j, M.NT) * ts * ts;
   for (int n = w; n < BLK; n += 4) {
     const int64_t col = (int64_t)v * BLK + n;
-    const double* Lc = L + col * ts;
+    const OT* Lc = L + col * ts;
     double s = 0.0;
-    for (int64_t r = lane; r < ts; r += 64) s += Lc[r] * ak[r];
+    for (int64_t r = lane; r < ts; r += 64) s += (double)Lc[r] * ak[r];
     s = wave_sum(s);
     if (lane == 0) rhs[j * ts + col] -= s;
   }
@@ -365,8 +369,8 @@ __global__ __launch_bounds__(256) void k_gemv_bwd(const double* __restrict__ til
 
 // w = L e on the lower tiles (diagonal tiles read below their diagonal only);
 // one 128-row block per workgroup
-__global__ __launch_bounds__(256) void k_trmv_lower(const double* __restrict__ tiles, int64_t ts,
-                                                    const double* __restrict__ e, double* __restrict__ w) {
+__global__ __launch_bounds__(256) void k_trmv_lower(TileMat M, const double* __restrict__ e, double* __restrict__ w) {
+  const int64_t ts = M.ts;
   __shared__ double red[256];
   const int T = (int)(ts / BLK);
   const int64_t g = blockIdx.x;
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(256) void k_trmv_lower(const double* __restrict__ t
   const int64_t row = u * BLK + r;
   double s = 0.0;
   for (int64_t j = 0; j <= i; ++j) {
-    const double* L = tiles + (tri(i) + j) * ts * ts + row;
+    const double* L = tptr(M, i, j) + row;
     const double* ej = e + j * ts;
     const int64_t qmax = (j == i) ? row : ts - 1;
     for (int64_t q = h; q <= qmax; q += 2) s += L[q * ts] * ej[q];
@@ -436,13 +440,13 @@ __global__ void k_copy_f64(double* __restrict__ dst, const double* __restrict__ 
 }
 
 // dst[k] = lower part of diagonal tile k (zeros above the diagonal), k < NT
-__global__ void k_copy_diag_lower(double* __restrict__ dst, const double* __restrict__ tiles, int64_t ts, int64_t NT) {
+__global__ void k_copy_diag_lower(double* __restrict__ dst, const double* __restrict__ diag, int64_t ts, int64_t NT) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tt = ts * ts;
   if (e >= NT * tt) return;
   const int64_t k = e / tt, q = e % tt;
   const int64_t r = q % ts, c = q / ts;
-  dst[e] = (r >= c) ? tiles[(tri(k) + k) * tt + q] : 0.0;
+  dst[e] = (r >= c) ? diag[k * tt + q] : 0.0;
 }
 
 // dst[k] block (c, c) = dinv[k][c] for every diagonal tile k
@@ -453,12 +457,6 @@ __global__ void k_put_dinv(double* __restrict__ dst, const double* __restrict__ 
   const int64_t k = e / (BLK * BLK), q = e % (BLK * BLK);
   const int r = (int)(q % BLK), cc = (int)(q / BLK);
   dst[k * ts * ts + (int64_t)c * BLK + r + ((int64_t)c * BLK + cc) * ts] = dinv[(k * T + c) * BLK * BLK + q];
-}
-
-// diagonal tile k of the tile matrix = src (ts x ts)
-__global__ void k_put_diag_tile(double* __restrict__ tiles, const double* __restrict__ src, int64_t ts, int64_t k) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < ts * ts) tiles[(tri(k) + k) * ts * ts + e] = src[e];
 }
 
 // ------------------------------------------------------------- launchers
@@ -490,34 +488,43 @@ void launch_potrf_blk(double* A, int64_t lda, double* dinv, double* ldpart, unsi
   hipLaunchKernelGGL(k_potrf_blk, dim3(1), dim3(256), 0, s, A, lda, dinv, ldpart, info, col0);
 }
 
-void launch_trsv_fwd(const double* tiles, const double* Xd, int64_t ts, int64_t NT, int64_t nreal, double* rhs,
-                     double* y, hipStream_t s) {
+void launch_trsv_fwd(const TileMat& M, bool off32, const double* Xd, int64_t nreal, double* rhs, double* y,
+                     hipStream_t s) {
+  const int64_t ts = M.ts, NT = M.NT;
   const int T = (int)(ts / BLK);
   const size_t shm = (size_t)(ts + 256) * sizeof(double);
   const int64_t gmax = (nreal + BLK - 1) / BLK;  // row blocks holding real rows
   for (int64_t k = 0; k < NT; ++k) {
     hipLaunchKernelGGL(k_diag_apply_n, dim3(T), dim3(256), 0, s, Xd + k * ts * ts, ts, rhs + k * ts, y + k * ts);
     const int64_t g0 = (k + 1) * T;
-    if (gmax > g0)
-      hipLaunchKernelGGL(k_gemv_fwd, dim3((unsigned)(gmax - g0)), dim3(256), shm, s, tiles, ts, k, g0, y + k * ts,
-                         rhs);
+    if (gmax > g0) {
+      if (off32)
+        hipLaunchKernelGGL(k_gemv_fwd<float>, dim3((unsigned)(gmax - g0)), dim3(256), shm, s, M, k, g0, y + k * ts,
+                           rhs);
+      else
+        hipLaunchKernelGGL(k_gemv_fwd<double>, dim3((unsigned)(gmax - g0)), dim3(256), shm, s, M, k, g0, y + k * ts,
+                           rhs);
+    }
   }
 }
 
-void launch_trsv_bwd(const double* tiles, const double* Xd, int64_t ts, int64_t NT, double* rhs, double* a,
-                     hipStream_t s) {
+void launch_trsv_bwd(const TileMat& M, bool off32, const double* Xd, double* rhs, double* a, hipStream_t s) {
+  const int64_t ts = M.ts, NT = M.NT;
   const int T = (int)(ts / BLK);
   for (int64_t k = NT - 1; k >= 0; --k) {
     hipLaunchKernelGGL(k_diag_apply_t, dim3(T), dim3(256), 0, s, Xd + k * ts * ts, ts, rhs + k * ts, a + k * ts);
-    if (k > 0) hipLaunchKernelGGL(k_gemv_bwd, dim3((unsigned)(k * T)), dim3(256), 0, s, tiles, ts, k, a + k * ts, rhs);
+    if (k > 0) {
+      if (off32)
+        hipLaunchKernelGGL(k_gemv_bwd<float>, dim3((unsigned)(k * T)), dim3(256), 0, s, M, k, a + k * ts, rhs);
+      else
+        hipLaunchKernelGGL(k_gemv_bwd<double>, dim3((unsigned)(k * T)), dim3(256), 0, s, M, k, a + k * ts, rhs);
+    }
   }
 }
 
-void launch_trmv_lower(const double* tiles, int64_t ts, int64_t NT, int64_t nreal, const double* e, double* w,
-                       hipStream_t s) {
+void launch_trmv_lower(const TileMat& M, int64_t nreal, const double* e, double* w, hipStream_t s) {
   const int64_t gmax = (nreal + BLK - 1) / BLK;
-  (void)NT;
-  hipLaunchKernelGGL(k_trmv_lower, dim3((unsigned)gmax), dim3(256), 0, s, tiles, ts, e, w);
+  hipLaunchKernelGGL(k_trmv_lower, dim3((unsigned)gmax), dim3(256), 0, s, M, e, w);
 }
 
 void launch_finalize_loglik(const double* yv, int64_t n, const double* ldpart, int64_t nld, double* out,
@@ -541,16 +548,13 @@ void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_copy_f64, dim3(nb(n, 256)), dim3(256), 0, s, dst, src, n);
 }
 
-void launch_copy_diag_lower(double* dst, const double* tiles, int64_t ts, int64_t NT, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy_diag_lower, dim3(nb(NT * ts * ts, 256)), dim3(256), 0, s, dst, tiles, ts, NT);
+void launch_copy_diag_lower(double* dst, const double* diag, int64_t ts, int64_t NT, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_diag_lower, dim3(nb(NT * ts * ts, 256)), dim3(256), 0, s, dst, diag, ts, NT);
 }
 
 void launch_put_dinv(double* dst, const double* dinv, int64_t ts, int64_t NT, int c, hipStream_t s) {
   hipLaunchKernelGGL(k_put_dinv, dim3(nb(NT * BLK * BLK, 256)), dim3(256), 0, s, dst, dinv, ts, NT, c);
 }
 
-void launch_put_diag_tile(double* tiles, const double* src, int64_t ts, int64_t k, hipStream_t s) {
-  hipLaunchKernelGGL(k_put_diag_tile, dim3(nb(ts * ts, 256)), dim3(256), 0, s, tiles, src, ts, k);
-}
 
 }  // namespace exg

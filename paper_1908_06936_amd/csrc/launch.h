@@ -4,16 +4,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "common.h"
+
 namespace exg {
 
-inline double* tile_ptr_host(double* base, int64_t i, int64_t j, int64_t ts) {
-  return base + (i * (i + 1) / 2 + j) * ts * ts;
-}
 
 // k_matern.hip
 void launch_quad_table(const double theta[3], double* qt, double* cst, hipStream_t s);
-void launch_gen_tiles(double* tiles, int64_t ts, int64_t NT, int64_t nreal, const double* xs, const double* ys,
-                      const double* qt, const double* cst, hipStream_t s);
+void launch_gen_tiles(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* qt,
+                      const double* cst, const uint8_t* tag, hipStream_t s);
 void launch_gen_dense(double* cov, int64_t ldc, int64_t n, const double* x, const double* y, const double* qt,
                       const double* cst, hipStream_t s);
 
@@ -24,31 +23,28 @@ void launch_sort_locations(const double* x, const double* y, const double* z, in
 void launch_scatter(const double* v, const int32_t* perm, int64_t n, double* out, hipStream_t s);
 void launch_potrf_blk(double* A, int64_t lda, double* dinv, double* ldpart, unsigned long long* info, int64_t col0,
                       hipStream_t s);
-void launch_trsv_fwd(const double* tiles, const double* Xd, int64_t ts, int64_t NT, int64_t nreal, double* rhs,
-                     double* y, hipStream_t s);
-void launch_trsv_bwd(const double* tiles, const double* Xd, int64_t ts, int64_t NT, double* rhs, double* a,
+void launch_trsv_fwd(const TileMat& M, bool off32, const double* Xd, int64_t nreal, double* rhs, double* y,
                      hipStream_t s);
-void launch_trmv_lower(const double* tiles, int64_t ts, int64_t NT, int64_t nreal, const double* e, double* w,
-                       hipStream_t s);
+void launch_trsv_bwd(const TileMat& M, bool off32, const double* Xd, double* rhs, double* a, hipStream_t s);
+void launch_trmv_lower(const TileMat& M, int64_t nreal, const double* e, double* w, hipStream_t s);
 void launch_finalize_loglik(const double* yv, int64_t n, const double* ldpart, int64_t nld, double* out,
                             hipStream_t s);
 void launch_finalize_grad(const double* part, int64_t nparts, double* out, hipStream_t s);
 void launch_fill_info(unsigned long long* info, hipStream_t s);
 void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
-void launch_copy_diag_lower(double* dst, const double* tiles, int64_t ts, int64_t NT, hipStream_t s);
+void launch_copy_diag_lower(double* dst, const double* diag, int64_t ts, int64_t NT, hipStream_t s);
 void launch_put_dinv(double* dst, const double* dinv, int64_t ts, int64_t NT, int c, hipStream_t s);
-void launch_put_diag_tile(double* tiles, const double* src, int64_t ts, int64_t k, hipStream_t s);
 
 // k_gemm.hip
-void launch_chol_update(double* tiles, int64_t ts, int64_t NT, int64_t k, int64_t nreal, hipStream_t s);
-void launch_panel(double* tiles, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k, double* ldpart_k,
-                  unsigned long long* info, hipStream_t s);
-void launch_diag_inverses(double* Xd, const double* tiles, const double* dinv, int64_t ts, int64_t NT, hipStream_t s);
-void launch_trtri_step(double* tiles, const double* Xk, double* P, int64_t ts, int64_t NT, int64_t k, int64_t nreal,
-                       hipStream_t s);
+void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, bool diag_only,
+                        hipStream_t s);
+void launch_panel(double* Dk, double* below, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k,
+                  double* ldpart_k, unsigned long long* info, hipStream_t s);
+void launch_diag_inverses(double* Xd, const double* diag, const double* dinv, int64_t ts, int64_t NT, hipStream_t s);
+void launch_trtri_step(const TileMat& M, const double* Xk, double* P, int64_t k, int64_t nreal, hipStream_t s);
 int64_t lauum_blocks(int64_t ts, int64_t NT);
-void launch_lauum_contract(const double* X, int64_t ts, int64_t NT, int64_t nreal, const double* xs, const double* ys,
-                           const double* av, const double* qt, const double* cst, double* part, hipStream_t s);
+void launch_lauum_contract(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* av,
+                           const double* qt, const double* cst, double* part, hipStream_t s);
 
 }  // namespace exg
