@@ -167,6 +167,32 @@ def main() -> int:
         "loglik": lls[-1][0],
         "grad": lls[-1][1],
     }
+    # l(theta) alone, FP64 and mixed precision (FP64 diagonal tiles, FP32
+    # off-diagonal tiles; BF16 beyond band * beta), same inputs
+    ctx.set_profiling(False)
+    ll_only = {}
+    for label, prec, band in (("fp64", "fp64", 3.0), ("mixed_fp32", "mixed", 0.0), ("mixed_bf16_3beta", "mixed", 3.0)):
+        ctx.set_mixed_policy(band)
+        st, v, info = ctx.loglik_status(X, Y, Z, theta, prec)  # warm-up / status
+        if st != 0:
+            ll_only[label] = {"status": exa.STATUS_NAMES.get(st, st), "info": info}
+            print(f"[bench] loglik-only {label}: status {st}", file=sys.stderr, flush=True)
+            continue
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            v = ctx.loglik(X, Y, Z, theta, prec)
+        torch.cuda.synchronize()
+        rate = args.steps / (time.perf_counter() - t1)
+        ll_only[label] = {"status": "OK", "evals_per_s": rate, "loglik": v,
+                          "frac_bf16_tiles": ctx.timings().get("frac_bf16")}
+        print(f"[bench] loglik-only {label}: {rate:.3f} evals/s", file=sys.stderr, flush=True)
+    ctx.set_mixed_policy(3.0)
+    l64 = ll_only["fp64"].get("loglik")
+    for label, d in ll_only.items():
+        if label != "fp64" and "loglik" in d and l64 is not None:
+            d["rel_err_vs_fp64"] = abs(d["loglik"] - l64) / abs(l64)
+    result["loglik_only"] = ll_only
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(n, theta, args.cpu_sample)
     print(json.dumps(result))

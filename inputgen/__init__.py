@@ -73,3 +73,19 @@ def clusters(n_per: int, n_clusters: int, width: float, separation: float, seed:
 
 def shuffled(n: int, seed: int = 0):
     return np.random.default_rng(seed + 104729).permutation(n)
+
+
+def corner_clusters(n_per: int, width: float, separation: float, seed: int = 0):
+    """Four square clusters of side ``width`` at the corners of a square of
+    side ``separation``; labels 0..3, points shuffled."""
+    rng = np.random.default_rng(seed)
+    xs, ys, lab = [], [], []
+    for c, (cx, cy) in enumerate([(0.0, 0.0), (separation, 0.0), (0.0, separation), (separation, separation)]):
+        xs.append(cx + rng.random(n_per) * width)
+        ys.append(cy + rng.random(n_per) * width)
+        lab.append(np.full(n_per, c))
+    x = np.concatenate(xs)
+    y = np.concatenate(ys)
+    lab = np.concatenate(lab)
+    perm = rng.permutation(x.size)
+    return x[perm], y[perm], lab[perm]

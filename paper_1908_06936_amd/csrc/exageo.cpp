@@ -25,15 +25,17 @@ constexpr int NEV = 512;                     // profiling events
 struct Plan {
   int64_t n = 0, ts = 0, NT = 0, T = 0, npad = 0, P = 0;
   bool grad = false;
+  bool mixed = false;
   size_t off_diag = 0, off_offt = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
-         off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0;
+         off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_tag = 0,
+         off_tbox = 0;
   size_t bytes = 0;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Plan make_plan(int64_t n, int64_t ts, int want_grad) {
+Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64) {
   Plan p;
   p.n = n;
   p.ts = ts;
@@ -43,6 +45,7 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad) {
   p.P = 2048;
   while (p.P < p.npad) p.P <<= 1;
   p.grad = want_grad != 0;
+  p.mixed = precision == EXAGEO_MIXED;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -51,7 +54,13 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad) {
   };
   const size_t tt = (size_t)ts * ts;
   p.off_diag = take((size_t)p.NT * tt * 8);
-  p.off_offt = take((size_t)std::max<int64_t>(1, p.NT * (p.NT - 1) / 2) * tt * 8);
+  const size_t noff = (size_t)std::max<int64_t>(1, p.NT * (p.NT - 1) / 2);
+  p.off_offt = take(noff * tt * (p.mixed ? 4 : 8));
+  if (p.mixed) {
+    p.off_pbuf = take((size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8);
+    p.off_tag = take(noff);
+    p.off_tbox = take((size_t)p.NT * 4 * 8);
+  }
   p.off_xd = take((size_t)p.NT * tt * 8);
   p.off_ptmp = p.grad ? take((size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8) : 0;
   p.off_dinv = take((size_t)p.NT * p.T * BLKH * BLKH * 8);
@@ -93,6 +102,11 @@ struct exageo_ctx {
   double* hres = nullptr;
   // current plan and sorted-location cache key (only valid inside one call or an MLE run)
   Plan plan;
+  // mixed precision: tile bounding boxes of the sorted locations (host copy)
+  // and pinned staging for the per-tile precision tags
+  std::vector<double> tbox;
+  uint8_t* htag = nullptr;
+  size_t htag_bytes = 0;
   // profiling
   hipEvent_t ev[NEV];
   int nev_created = 0;
@@ -180,6 +194,47 @@ exageo_status prepare_locations(exageo_ctx* c, const Plan& p, const double* x, c
                              at<double>(c, p.off_xs), at<double>(c, p.off_ys), at<double>(c, p.off_zs),
                              at<int32_t>(c, p.off_perm), c->stream);
   HIPCHK(c, hipGetLastError());
+  if (p.mixed) {
+    // bounding boxes of the location blocks of the tiles, for the precision map
+    exg::launch_tile_bbox(at<double>(c, p.off_xs), at<double>(c, p.off_ys), p.ts, p.NT, p.n,
+                          at<double>(c, p.off_tbox), c->stream);
+    c->tbox.assign((size_t)p.NT * 4, 0.0);
+    HIPCHK(c, hipMemcpyAsync(c->tbox.data(), at<double>(c, p.off_tbox), (size_t)p.NT * 4 * 8, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return EXAGEO_OK;
+}
+
+// Precision of every off-diagonal tile (0 = FP32, 1 = BF16): BF16 when the
+// minimum distance between the bounding boxes of the two location blocks is
+// at least band_factor * beta.  Returns the BF16 fraction.
+exageo_status upload_tags(exageo_ctx* c, const Plan& p, double beta, double* frac_bf16) {
+  const size_t noff = (size_t)std::max<int64_t>(1, p.NT * (p.NT - 1) / 2);
+  if (c->htag_bytes < noff) {
+    if (c->htag) HIPCHK(c, hipHostFree(c->htag));
+    c->htag = nullptr;
+    HIPCHK(c, hipHostMalloc((void**)&c->htag, noff));
+    c->htag_bytes = noff;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // previous upload consumed
+  const double band = c->band_factor * beta;
+  int64_t nbf = 0, ntot = 0;
+  for (int64_t j = 0; j < p.NT; ++j) {
+    const double* bj = &c->tbox[4 * j];
+    for (int64_t i = j + 1; i < p.NT; ++i) {
+      const double* bi = &c->tbox[4 * i];
+      const double dx = std::max(0.0, std::max(bi[0] - bj[1], bj[0] - bi[1]));
+      const double dy = std::max(0.0, std::max(bi[2] - bj[3], bj[2] - bi[3]));
+      const bool bf = c->band_factor > 0.0 && std::sqrt(dx * dx + dy * dy) >= band;
+      c->htag[exg::off_index(i, j, p.NT)] = bf ? 1 : 0;
+      nbf += bf;
+      ++ntot;
+    }
+  }
+  if (p.NT == 1) c->htag[0] = 0;
+  HIPCHK(c, hipMemcpyAsync(at<uint8_t>(c, p.off_tag), c->htag, noff, hipMemcpyHostToDevice, c->stream));
+  *frac_bf16 = ntot ? (double)nbf / (double)ntot : 0.0;
   return EXAGEO_OK;
 }
 
@@ -201,21 +256,45 @@ double* below_fp64(const exg::TileMat& M, int64_t k) {
 exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
   const exg::TileMat M = tilemat(c, p);
   const int64_t tt = p.ts * p.ts;
+  const uint8_t* tag = nullptr;
+  c->timings[10] = p.mixed ? EXAGEO_MIXED : EXAGEO_FP64;
+  c->timings[11] = 0.0;
+  c->timings[12] = 0.0;
+  if (p.mixed) {
+    double fbf = 0.0;
+    exageo_status st = upload_tags(c, p, theta[1], &fbf);
+    if (st) return st;
+    tag = at<uint8_t>(c, p.off_tag);
+    c->timings[11] = fbf;
+    c->timings[12] = p.NT > 1 ? 1.0 - fbf : 0.0;
+  }
   exg::launch_quad_table(theta, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   exg::launch_fill_info(at<unsigned long long>(c, p.off_info), c->stream);
   exg::launch_gen_tiles(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), at<double>(c, p.off_qt),
-                        at<double>(c, p.off_cst), nullptr, c->stream);
+                        at<double>(c, p.off_cst), tag, c->stream);
   rec(c, 2);
   double upd_flops = 0.0;
   int nupd = 0;
+  double* pbuf = p.mixed ? at<double>(c, p.off_pbuf) : nullptr;
   for (int64_t k = 0; k < p.NT; ++k) {
-    double* below = (k + 1 < p.NT) ? below_fp64(M, k) : nullptr;
+    // FP64 column below the diagonal: in place, or widened into the panel buffer
+    double* below = nullptr;
+    if (k + 1 < p.NT) {
+      if (p.mixed) {
+        exg::launch_panel_gather(M, k, tag, pbuf, c->stream);
+        below = pbuf;
+      } else {
+        below = below_fp64(M, k);
+      }
+    }
     exg::launch_panel(M.diag + k * tt, below, p.ts, p.NT, k, p.n, at<double>(c, p.off_dinv) + k * p.T * BLKH * BLKH,
                       at<double>(c, p.off_ld) + k * p.T, at<unsigned long long>(c, p.off_info), c->stream);
+    if (p.mixed && k + 1 < p.NT) exg::launch_panel_scatter(M, k, tag, pbuf, c->stream);
     if (k + 1 < p.NT) {
       const int slot = EV_UPD0 + 2 * nupd;
       if (slot + 1 < c->nev_created) rec(c, slot);
-      exg::launch_chol_update(M, below, k, p.n, false, c->stream);
+      exg::launch_chol_update(M, below, k, p.n, p.mixed, c->stream);
+      if (p.mixed) exg::launch_update_lp(M, tag, k, p.n, c->stream);
       if (slot + 1 < c->nev_created) rec(c, slot + 1);
       ++nupd;
       // algorithmic flops of this update over the real rows
@@ -244,7 +323,10 @@ exageo_status solve_reduce(exageo_ctx* c, const Plan& p) {
   double* Xd = at<double>(c, p.off_xd);
   exg::launch_diag_inverses(Xd, M.diag, at<double>(c, p.off_dinv), p.ts, p.NT, c->stream);
   exg::launch_copy(rhs, at<double>(c, p.off_zs), p.npad, c->stream);
-  exg::launch_trsv_fwd(M, false, Xd, p.n, rhs, y, c->stream);
+  if (p.mixed)
+    exg::launch_trsv_fwd_lp(M, at<uint8_t>(c, p.off_tag), Xd, p.n, rhs, y, c->stream);
+  else
+    exg::launch_trsv_fwd(M, false, Xd, p.n, rhs, y, c->stream);
   exg::launch_finalize_loglik(y, p.n, at<double>(c, p.off_ld), p.NT * p.T, at<double>(c, p.off_out), c->stream);
   HIPCHK(c, hipGetLastError());
   rec(c, 4);
@@ -345,6 +427,7 @@ void exageo_destroy(exageo_ctx* c) {
   else (void)hipDeviceSynchronize();
   if (c->ws && c->ws_owned) (void)hipFree(c->ws);
   if (c->hres) (void)hipHostFree(c->hres);
+  if (c->htag) (void)hipHostFree(c->htag);
   for (int i = 0; i < c->nev_created; ++i) (void)hipEventDestroy(c->ev[i]);
   delete c;
 }
@@ -357,8 +440,7 @@ exageo_status exageo_set_stream(exageo_ctx* c, void* hip_stream) {
 
 size_t exageo_workspace_bytes(int64_t n, int64_t ts, int precision, int want_grad) {
   if (n < 1 || ts < BLKH || ts % BLKH != 0) return 0;
-  (void)precision;
-  return make_plan(n, ts, want_grad).bytes;
+  return make_plan(n, ts, want_grad, precision).bytes;
 }
 
 exageo_status exageo_set_workspace(exageo_ctx* c, void* dev_ptr, size_t bytes) {
@@ -469,10 +551,11 @@ static exageo_status loglik_common(exageo_ctx* c, int64_t n, const double* x, co
   if (n < 1 || !x || !y || !z || !theta_ok(theta) || !loglik || (want_grad && !grad))
     return fail(c, EXAGEO_EINVAL, "loglik: invalid argument");
   if (precision != EXAGEO_FP64 && precision != EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "unknown precision");
-  if (precision == EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "mixed precision not available in this build");
+  if (precision == EXAGEO_MIXED && want_grad)
+    return fail(c, EXAGEO_EINVAL, "the gradient is computed in FP64 only (precision must be EXAGEO_FP64)");
   if (n > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n too large");
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
-  Plan p = make_plan(n, c->ts, want_grad);
+  Plan p = make_plan(n, c->ts, want_grad, precision);
   exageo_status st = ensure_ws(c, p);
   if (st) return st;
   c->plan = p;
@@ -537,14 +620,15 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
     return fail(c, EXAGEO_EINVAL, "mle: invalid argument");
   if (method != EXAGEO_DFO && method != EXAGEO_LBFGSB) return fail(c, EXAGEO_EINVAL, "unknown method");
   if (precision != EXAGEO_FP64 && precision != EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "unknown precision");
-  if (precision == EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "mixed precision not available in this build");
+  if (precision == EXAGEO_MIXED && method == EXAGEO_LBFGSB)
+    return fail(c, EXAGEO_EINVAL, "the gradient method runs in FP64 only");
   for (int k = 0; k < 3; ++k) {
     if (!theta_ok(lb) || !theta_ok(ub) || lb[k] > ub[k]) return fail(c, EXAGEO_EINVAL, "mle: bad bounds");
     if (theta0 && (!(theta0[k] >= lb[k]) || !(theta0[k] <= ub[k]))) return fail(c, EXAGEO_EINVAL, "theta0 outside bounds");
   }
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
   const bool want_grad = method == EXAGEO_LBFGSB;
-  Plan p = make_plan(n, c->ts, want_grad);
+  Plan p = make_plan(n, c->ts, want_grad, precision);
   exageo_status st = ensure_ws(c, p);
   if (st) return st;
   c->plan = p;

@@ -508,6 +508,10 @@ void launch_trsv_fwd(const TileMat& M, bool off32, const double* Xd, int64_t nre
   }
 }
 
+void launch_diag_apply_n(const double* Xk, int64_t ts, const double* b, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_apply_n, dim3((unsigned)(ts / BLK)), dim3(256), 0, s, Xk, ts, b, out);
+}
+
 void launch_trsv_bwd(const TileMat& M, bool off32, const double* Xd, double* rhs, double* a, hipStream_t s) {
   const int64_t ts = M.ts, NT = M.NT;
   const int T = (int)(ts / BLK);

@@ -36,6 +36,17 @@ void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 void launch_copy_diag_lower(double* dst, const double* diag, int64_t ts, int64_t NT, hipStream_t s);
 void launch_put_dinv(double* dst, const double* dinv, int64_t ts, int64_t NT, int c, hipStream_t s);
 
+void launch_diag_apply_n(const double* Xk, int64_t ts, const double* b, double* out, hipStream_t s);
+
+// k_mixed.hip
+void launch_tile_bbox(const double* xs, const double* ys, int64_t ts, int64_t NT, int64_t nreal, double* box,
+                      hipStream_t s);
+void launch_panel_gather(const TileMat& M, int64_t k, const uint8_t* tag, double* pbuf, hipStream_t s);
+void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const double* pbuf, hipStream_t s);
+void launch_update_lp(const TileMat& M, const uint8_t* tag, int64_t k, int64_t nreal, hipStream_t s);
+void launch_trsv_fwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, int64_t nreal, double* rhs,
+                        double* y, hipStream_t s);
+
 // k_gemm.hip
 void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, bool diag_only,
                         hipStream_t s);
