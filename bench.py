@@ -193,6 +193,37 @@ def main() -> int:
         if label != "fp64" and "loglik" in d and l64 is not None:
             d["rel_err_vs_fp64"] = abs(d["loglik"] - l64) / abs(l64)
     result["loglik_only"] = ll_only
+
+    # the same comparison on a 200 x 200 jittered grid (n = 40,000), where
+    # the minimum spacing keeps the lower-precision tiles positive definite
+    xg, yg = inputgen.jittered_grid(200, seed=0)
+    Xg, Yg = torch.as_tensor(xg, device=dev), torch.as_tensor(yg, device=dev)
+    grid = {}
+    for th_g in ([1.0, 0.1, 0.5], [1.0, 0.03, 0.5]):
+        Zg = ctx.simulate(Xg, Yg, th_g, E)
+        key = f"beta={th_g[1]},nu={th_g[2]}"
+        grid[key] = {}
+        for label, prec, band in (("fp64", "fp64", 3.0), ("mixed_fp32", "mixed", 0.0),
+                                  ("mixed_bf16_3beta", "mixed", 3.0)):
+            ctx.set_mixed_policy(band)
+            st, v, info = ctx.loglik_status(Xg, Yg, Zg, th_g, prec)
+            if st != 0:
+                grid[key][label] = {"status": exa.STATUS_NAMES.get(st, st), "info": info}
+                continue
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                v = ctx.loglik(Xg, Yg, Zg, th_g, prec)
+            torch.cuda.synchronize()
+            grid[key][label] = {"status": "OK", "evals_per_s": args.steps / (time.perf_counter() - t1),
+                                "loglik": v, "frac_bf16_tiles": ctx.timings().get("frac_bf16")}
+        ref = grid[key]["fp64"].get("loglik")
+        for label, d in grid[key].items():
+            if label != "fp64" and "loglik" in d and ref is not None:
+                d["rel_err_vs_fp64"] = abs(d["loglik"] - ref) / abs(ref)
+        print(f"[bench] jittered grid {key} done", file=sys.stderr, flush=True)
+    ctx.set_mixed_policy(3.0)
+    result["loglik_only_jittered_grid_200x200"] = grid
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(n, theta, args.cpu_sample)
     print(json.dumps(result))
