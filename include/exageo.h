@@ -148,11 +148,12 @@ exageo_status exageo_mle(exageo_ctx *ctx, int64_t n, const double *x, const doub
  * exageo_set_profiling(ctx, 1) (adds HIP events between phases).
  * out receives up to nmax doubles in this order:
  *   0 total ms (first to last event), 1 sort+prep ms, 2 generation ms,
- *   3 Cholesky ms, 4 trailing-update GEMM kernel ms (sum of its launches),
- *   5 trailing-update GEMM flops, 6 solve+reduce ms, 7 gradient ms,
- *   8 Cholesky flops (n^3/3 + n^2/2 + n/6 of the padded problem, FP64
- *   equivalent), 9 number of trailing-update launches, 10 precision used,
- *   11 fraction of off-diagonal tiles in BF16, 12 fraction in FP32.
+ *   3 Cholesky ms, 4 trailing-update ms (event span of each step's update
+ *   launches, summed over steps), 5 trailing-update flops (real rows),
+ *   6 solve+reduce ms, 7 gradient ms, 8 Cholesky flops (n^3/3 + n^2/2 + n/6,
+ *   FP64 equivalent), 9 number of FP64 trailing-update (k_chol_update)
+ *   launches, 10 precision used, 11 fraction of off-diagonal tiles in BF16,
+ *   12 fraction in FP32, 13 number of factorisation steps with an update.
  * Returns the number of values written. */
 int exageo_get_timings(const exageo_ctx *ctx, double *out, int nmax);
 exageo_status exageo_set_profiling(exageo_ctx *ctx, int on);

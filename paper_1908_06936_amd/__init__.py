@@ -136,7 +136,7 @@ class Context:
         buf = (ctypes.c_double * 16)()
         m = self._lib.exageo_get_timings(self._h, buf, 16)
         keys = ["total_ms", "prep_ms", "gen_ms", "chol_ms", "update_kernel_ms", "update_flops", "solve_ms",
-                "grad_ms", "chol_flops", "update_launches", "precision", "frac_bf16", "frac_fp32"]
+                "grad_ms", "chol_flops", "update_launches", "precision", "frac_bf16", "frac_fp32", "update_steps"]
         return {k: buf[i] for i, k in enumerate(keys[:m])}
 
     # ---------------------------------------------------------- operations

@@ -59,6 +59,28 @@ __device__ __forceinline__ void tri_decode(int64_t p, int64_t* a, int64_t* b) {
   *b = p - tri(r);
 }
 
+// Which (target row, target column) tile pairs of step k one update launch
+// covers.  Pairs are offsets (a, c), c <= a, below the step's first trailing
+// tile; the first trailing column (c = 0) is updated apart from the rest so
+// that the next panel can be factored while the rest of the update runs.
+enum UpdatePart { UPD_ALL = 0, UPD_FIRST_COLUMN = 1, UPD_REST = 2 };
+enum PairMap { PAIRS_TRI = 0, PAIRS_DIAG = 1, PAIRS_COL = 2 };
+
+// pair group p -> (a, c): PAIRS_TRI the p-th lower pair shifted by off on
+// both sides, PAIRS_DIAG a = c = p + off, PAIRS_COL a = p + off and c = 0
+__device__ __forceinline__ void pair_map(int mode, int64_t off, int64_t p, int64_t* a, int64_t* c) {
+  if (mode == PAIRS_DIAG) {
+    *a = *c = p + off;
+  } else if (mode == PAIRS_COL) {
+    *a = p + off;
+    *c = 0;
+  } else {
+    tri_decode(p, a, c);
+    *a += off;
+    *c += off;
+  }
+}
+
 // v_mfma_f64_16x16x4f64 lane layout (checked on gfx950):
 //   operand X (first):  lane l holds X[l % 16][l / 16]      (16 x 4)
 //   operand Y (second): lane l holds Y[l / 16][l % 16]      (4 x 16)

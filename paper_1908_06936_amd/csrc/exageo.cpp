@@ -28,7 +28,7 @@ struct Plan {
   bool mixed = false;
   size_t off_diag = 0, off_offt = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
-         off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_tag = 0,
+         off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_p32 = 0, off_tag = 0,
          off_tbox = 0;
   size_t bytes = 0;
 };
@@ -57,7 +57,9 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
   const size_t noff = (size_t)std::max<int64_t>(1, p.NT * (p.NT - 1) / 2);
   p.off_offt = take(noff * tt * (p.mixed ? 4 : 8));
   if (p.mixed) {
-    p.off_pbuf = take((size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8);
+    // two halves each: the panel of step k + 1 is built while step k's update reads step k's
+    p.off_pbuf = take(2 * (size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8);
+    p.off_p32 = take(2 * (size_t)std::max<int64_t>(1, p.NT - 1) * tt * 4);
     p.off_tag = take(noff);
     p.off_tbox = take((size_t)p.NT * 4 * 8);
   }
@@ -107,6 +109,9 @@ struct exageo_ctx {
   std::vector<double> tbox;
   uint8_t* htag = nullptr;
   size_t htag_bytes = 0;
+  // side stream (default priority) for the lookahead panel, and its events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_col = nullptr, ev_panel = nullptr;
   // profiling
   hipEvent_t ev[NEV];
   int nev_created = 0;
@@ -275,36 +280,53 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
   rec(c, 2);
   double upd_flops = 0.0;
   int nupd = 0;
-  double* pbuf = p.mixed ? at<double>(c, p.off_pbuf) : nullptr;
-  for (int64_t k = 0; k < p.NT; ++k) {
-    // FP64 column below the diagonal: in place, or widened into the panel buffer
+  // Lookahead of one panel: step k first updates the first trailing column
+  // (k + 1) on the main stream; the side stream then factors panel k + 1
+  // while the main stream runs the rest of step k's update.  In mixed
+  // precision the FP64 panel buffer and its FP32 copy alternate between two
+  // halves so that panel k + 1 never overwrites the operands of step k.
+  hipStream_t S = c->stream, S2 = c->side;
+  const size_t phalf = (size_t)std::max<int64_t>(1, p.NT - 1) * tt;
+  auto panel = [&](int64_t k, hipStream_t s) -> double* {
     double* below = nullptr;
     if (k + 1 < p.NT) {
       if (p.mixed) {
-        exg::launch_panel_gather(M, k, tag, pbuf, c->stream);
-        below = pbuf;
+        below = at<double>(c, p.off_pbuf) + (k & 1) * phalf;
+        exg::launch_panel_gather(M, k, tag, below, s);
       } else {
         below = below_fp64(M, k);
       }
     }
     exg::launch_panel(M.diag + k * tt, below, p.ts, p.NT, k, p.n, at<double>(c, p.off_dinv) + k * p.T * BLKH * BLKH,
-                      at<double>(c, p.off_ld) + k * p.T, at<unsigned long long>(c, p.off_info), c->stream);
-    if (p.mixed && k + 1 < p.NT) exg::launch_panel_scatter(M, k, tag, pbuf, c->stream);
-    if (k + 1 < p.NT) {
-      const int slot = EV_UPD0 + 2 * nupd;
-      if (slot + 1 < c->nev_created) rec(c, slot);
-      exg::launch_chol_update(M, below, k, p.n, p.mixed, c->stream);
-      if (p.mixed) exg::launch_update_lp(M, tag, k, p.n, c->stream);
-      if (slot + 1 < c->nev_created) rec(c, slot + 1);
-      ++nupd;
-      // algorithmic flops of this update over the real rows
-      for (int64_t j = k + 1; j < p.NT; ++j) {
-        const double rj = (double)std::min<int64_t>(p.ts, p.n - j * p.ts);
-        upd_flops += rj * (rj + 1.0) * (double)p.ts;  // SYRK
-        for (int64_t i = j + 1; i < p.NT; ++i) {
-          const double ri = (double)std::min<int64_t>(p.ts, p.n - i * p.ts);
-          upd_flops += 2.0 * ri * rj * (double)p.ts;
-        }
+                      at<double>(c, p.off_ld) + k * p.T, at<unsigned long long>(c, p.off_info), s);
+    if (p.mixed && k + 1 < p.NT)
+      exg::launch_panel_scatter(M, k, tag, below, at<float>(c, p.off_p32) + (k & 1) * phalf, s);
+    return below;
+  };
+  double* below = panel(0, S);
+  for (int64_t k = 0; k + 1 < p.NT; ++k) {
+    float* p32 = p.mixed ? at<float>(c, p.off_p32) + (k & 1) * phalf : nullptr;
+    const int slot = EV_UPD0 + 2 * (int)k;
+    if (slot + 1 < c->nev_created) rec(c, slot);
+    exg::launch_chol_update(M, below, k, p.n, p.mixed, exg::UPD_FIRST_COLUMN, S);
+    if (p.mixed) exg::launch_update_lp(M, tag, p32, k, p.n, exg::UPD_FIRST_COLUMN, S);
+    HIPCHK(c, hipEventRecord(c->ev_col, S));
+    HIPCHK(c, hipStreamWaitEvent(S2, c->ev_col, 0));
+    double* next = panel(k + 1, S2);
+    HIPCHK(c, hipEventRecord(c->ev_panel, S2));
+    exg::launch_chol_update(M, below, k, p.n, p.mixed, exg::UPD_REST, S);
+    if (p.mixed) exg::launch_update_lp(M, tag, p32, k, p.n, exg::UPD_REST, S);
+    if (slot + 1 < c->nev_created) rec(c, slot + 1);
+    HIPCHK(c, hipStreamWaitEvent(S, c->ev_panel, 0));
+    below = next;
+    nupd += p.NT - k - 1 >= 2 ? 2 : 1;  // launches of k_chol_update in this step
+    // algorithmic flops of this update over the real rows
+    for (int64_t j = k + 1; j < p.NT; ++j) {
+      const double rj = (double)std::min<int64_t>(p.ts, p.n - j * p.ts);
+      upd_flops += rj * (rj + 1.0) * (double)p.ts;  // SYRK
+      for (int64_t i = j + 1; i < p.NT; ++i) {
+        const double ri = (double)std::min<int64_t>(p.ts, p.n - i * p.ts);
+        upd_flops += 2.0 * ri * rj * (double)p.ts;
       }
     }
   }
@@ -312,6 +334,7 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
   rec(c, 3);
   c->timings[5] = upd_flops;
   c->timings[9] = nupd;
+  c->timings[13] = (double)std::max<int64_t>(0, p.NT - 1);
   return EXAGEO_OK;
 }
 
@@ -383,7 +406,7 @@ void finish_timings(exageo_ctx* c, const Plan& p, bool grad) {
   c->timings[2] = ev_ms(c, 1, 2);
   c->timings[3] = ev_ms(c, 2, 3);
   double upd = 0.0;
-  for (int i = 0; i < (int)c->timings[9]; ++i) {
+  for (int i = 0; i < (int)c->timings[13]; ++i) {
     const int slot = EV_UPD0 + 2 * i;
     if (slot + 1 < c->nev_created) upd += ev_ms(c, slot, slot + 1);
   }
@@ -412,8 +435,11 @@ exageo_status exageo_create(exageo_ctx** out, int device, int64_t ts, void* hip_
   c->device = device;
   c->ts = ts;
   c->stream = (hipStream_t)hip_stream;
-  if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void**)&c->hres, 64 * sizeof(double)) != hipSuccess) {
-    delete c;
+  if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void**)&c->hres, 64 * sizeof(double)) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_col, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_panel, hipEventDisableTiming) != hipSuccess) {
+    exageo_destroy(c);
     return EXAGEO_EDEVICE;
   }
   *out = c;
@@ -429,6 +455,12 @@ void exageo_destroy(exageo_ctx* c) {
   if (c->hres) (void)hipHostFree(c->hres);
   if (c->htag) (void)hipHostFree(c->htag);
   for (int i = 0; i < c->nev_created; ++i) (void)hipEventDestroy(c->ev[i]);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->ev_col) (void)hipEventDestroy(c->ev_col);
+  if (c->ev_panel) (void)hipEventDestroy(c->ev_panel);
   delete c;
 }
 

@@ -30,7 +30,7 @@ namespace exg {
 // diag_only: update only the diagonal tiles (j, j) (mixed precision, where the
 // off-diagonal targets are updated by the lower-precision kernels).
 __global__ __launch_bounds__(256, 2) void k_chol_update(TileMat M, const double* __restrict__ below, int T, int64_t k,
-                                                        int64_t nreal, int64_t nb, int diag_only) {
+                                                        int64_t nreal, int64_t nb, int mode, int64_t off) {
   __shared__ double sm[GEMM_LDS];
   const int64_t ts = M.ts;
   const int64_t b = blockIdx.x;
@@ -39,11 +39,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_update(TileMat M, const double*
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
   int64_t a, c;
-  if (diag_only) {
-    a = c = p;
-  } else {
-    tri_decode(p, &a, &c);
-  }
+  pair_map(mode, off, p, &a, &c);
   const int64_t i = k + 1 + a, j = k + 1 + c;
   if (i == j && u < v) return;
   if (i * ts + u * BLK >= nreal || j * ts + v * BLK >= nreal) return;  // padding: update is zero
@@ -300,14 +296,27 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract(TileMat M, int T, int
 }
 
 // ------------------------------------------------------------- launchers
-void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, bool diag_only,
+void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, bool diag_only, int part,
                         hipStream_t s) {
   const int T = (int)(M.ts / BLK);
-  const int64_t m = M.NT - k - 1;
+  const int64_t m = M.NT - k - 1;  // trailing tiles
   if (m <= 0) return;
-  const int64_t nblk = (diag_only ? m : m * (m + 1) / 2) * T * T;
-  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, M, below, T, k, nreal, nblk,
-                     diag_only ? 1 : 0);
+  int mode;
+  int64_t off, npairs;
+  if (diag_only) {
+    mode = PAIRS_DIAG;
+    off = part == UPD_REST ? 1 : 0;
+    npairs = part == UPD_ALL ? m : part == UPD_FIRST_COLUMN ? 1 : m - 1;
+  } else if (part == UPD_ALL) {
+    mode = PAIRS_TRI, off = 0, npairs = m * (m + 1) / 2;
+  } else if (part == UPD_FIRST_COLUMN) {
+    mode = PAIRS_COL, off = 0, npairs = m;
+  } else {
+    mode = PAIRS_TRI, off = 1, npairs = (m - 1) * m / 2;
+  }
+  if (npairs <= 0) return;
+  const int64_t nblk = npairs * T * T;
+  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, M, below, T, k, nreal, nblk, mode, off);
 }
 
 void launch_panel(double* Dk, double* below, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k,

@@ -6,12 +6,13 @@
 // Step k of the factorisation:
 //   1. the column-k tiles below the diagonal are widened into an FP64 panel
 //      buffer, the panel is factored by the FP64 kernels and written back,
-//      rounded to nearest even into each tile's precision;
+//      rounded to nearest even into each tile's precision and, for the
+//      update, to FP32 in a panel copy;
 //   2. diagonal targets A_jj -= A_jk A_jk^T run on FP64 MFMA from the FP64
 //      panel buffer (k_chol_update with diag_only);
 //   3. off-diagonal targets A_ij -= A_ik A_jk^T run on FP32 MFMA with FP32
-//      accumulation; BF16 operands are widened exactly, BF16 targets rounded
-//      back to nearest even.
+//      accumulation from the FP32 panel copy; BF16 targets are widened
+//      exactly and rounded back to nearest even.
 // The solves read the stored tiles and accumulate in FP64; log det Sigma and
 // z^T Sigma^-1 z are FP64 sums.
 #include <float.h>
@@ -21,8 +22,6 @@
 
 namespace exg {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -83,9 +82,10 @@ __global__ void k_panel_gather(TileMat M, int64_t k, const uint8_t* __restrict__
   pbuf[e] = tag[idx] ? (double)bf16_to_f32(((const uint16_t*)src)[o]) : (double)src[o];
 }
 
-// tile (k + 1 + q, k) = pbuf tile q rounded to nearest even in its precision
+// tile (k + 1 + q, k) = pbuf tile q rounded to nearest even in its precision;
+// p32 tile q = pbuf tile q rounded to FP32 (the operands of the FP32 update)
 __global__ void k_panel_scatter(TileMat M, int64_t k, const uint8_t* __restrict__ tag, const double* __restrict__ pbuf,
-                                int64_t count) {
+                                float* __restrict__ p32, int64_t count) {
   const int64_t tt = M.ts * M.ts;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= count * tt) return;
@@ -93,6 +93,7 @@ __global__ void k_panel_scatter(TileMat M, int64_t k, const uint8_t* __restrict_
   const int64_t idx = off_index(k + 1 + q, k, M.NT);
   float* dst = (float*)M.off + idx * tt;
   const float f = (float)pbuf[e];
+  p32[e] = f;
   if (tag[idx])
     ((uint16_t*)dst)[o] = f32_to_bf16(f);
   else
@@ -100,19 +101,27 @@ __global__ void k_panel_scatter(TileMat M, int64_t k, const uint8_t* __restrict_
 }
 
 // ------------------------------------------------ FP32 MFMA trailing update
-constexpr int FBK = 32;        // k-depth of one LDS stage
+constexpr int FBK = 16;        // k-depth of one LDS stage
 constexpr int FLDP = BLK + 4;  // padded LDS row (floats)
 constexpr int FLDS = 2 * 2 * FBK * FLDP;
 
-__device__ __forceinline__ v4f mfma32(float x, float y, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ v16f mfma32x32(float x, float y, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, c, 0, 0, 0);
 }
 
-// C_ij -= A_ik A_jk^T for the off-diagonal targets k < j < i < NT.
-// v_mfma_f32_16x16x4f32: operand X lane l holds X[l % 16][l / 16], operand Y
-// holds Y[l / 16][l % 16], D = X Y has lane l, register r at D[4 (l/16) + r][l % 16].
-__global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* __restrict__ tag, int T, int64_t k,
-                                                      int64_t nreal, int64_t nb) {
+// C_ij -= L_ik L_jk^T for the off-diagonal targets k < j < i < NT, with the
+// operands taken from the FP32 rounding of the FP64 panel (p32 tile q holds
+// L_{k+1+q, k}), so that a BF16-stored panel tile never feeds its rounding
+// error into targets near the diagonal.  One 256-thread block computes one
+// 128 x 128 block of a target tile; wave (wr, wc) owns its 64 x 64 quarter as
+// 2 x 2 products on v_mfma_f32_32x32x2f32.  That instruction takes operand X
+// lane l as X[l % 32][l / 32] and Y lane l as Y[l / 32][l % 32]; D = X Y has
+// lane l, register r at D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+__global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* __restrict__ tag,
+                                                      const float* __restrict__ p32, int T, int64_t k,
+                                                      int64_t nreal, int64_t nb, int mode, int64_t off) {
   __shared__ float sm[FLDS];
   const int64_t ts = M.ts, tt = ts * ts;
   const int64_t b = blockIdx.x;
@@ -121,121 +130,85 @@ __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* 
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
   int64_t a, c;
-  tri_decode(p, &a, &c);  // c <= a
+  pair_map(mode, off, p, &a, &c);  // c <= a
   const int64_t i = k + 2 + a, j = k + 1 + c;
   if (i * ts + u * BLK >= nreal) return;  // padded rows: update is zero
-  const int64_t ia = off_index(i, k, M.NT), ib = off_index(j, k, M.NT), ic = off_index(i, j, M.NT);
-  const bool abf = tag[ia] != 0, bbf = tag[ib] != 0, cbf = tag[ic] != 0;
-  const float* A = (const float*)M.off + ia * tt;
-  const float* B = (const float*)M.off + ib * tt;
+  const float* A = p32 + (a + 1) * tt + u * BLK;
+  const float* B = p32 + c * tt + v * BLK;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int NL = FBK * BLK / 4 / 256;  // float4 loads per thread per operand and stage
+  f4 ra0[NL], rb0[NL], ra1[NL], rb1[NL];
   float* sA = sm;
   float* sB = sm + 2 * FBK * FLDP;
-  // raw 16-byte chunks of a stage: FP32 tiles use 4 chunks of 4 values per
-  // thread, BF16 tiles 2 chunks of 8 values
-  u4 ra0[4], rb0[4], ra1[4], rb1[4];
-  auto gl = [&](const float* X, bool bf, int rowoff, int k0, u4 (&r)[4]) {
-    if (!bf) {
+  auto gload = [&](int k0, f4 (&ra)[NL], f4 (&rb)[NL]) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int idx = t + 256 * s, kk = idx >> 5, m4 = idx & 31;
-        r[s] = *(const u4*)(X + rowoff + 4 * m4 + (int64_t)(k0 + kk) * ts);
-      }
-    } else {
-      const uint16_t* Xh = (const uint16_t*)X;
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int idx = t + 256 * s, kk = idx >> 4, m8 = idx & 15;
-        r[s] = *(const u4*)(Xh + rowoff + 8 * m8 + (int64_t)(k0 + kk) * ts);
-      }
+    for (int s = 0; s < NL; ++s) {
+      const int idx = t + 256 * s, kk = idx >> 5, m4 = idx & 31;
+      ra[s] = *(const f4*)(A + 4 * m4 + (int64_t)(k0 + kk) * ts);
+      rb[s] = *(const f4*)(B + 4 * m4 + (int64_t)(k0 + kk) * ts);
     }
   };
-  auto st = [&](float* S, bool bf, u4 (&r)[4]) {
-    if (!bf) {
+  auto sstore = [&](int buf, f4 (&ra)[NL], f4 (&rb)[NL]) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int idx = t + 256 * s, kk = idx >> 5, m4 = idx & 31;
-        *(u4*)(S + kk * FLDP + 4 * m4) = r[s];
-      }
-    } else {
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int idx = t + 256 * s, kk = idx >> 4, m8 = idx & 15;
-        u4 lo, hi;
-        lo.x = r[s].x << 16;
-        lo.y = r[s].x & 0xffff0000u;
-        lo.z = r[s].y << 16;
-        lo.w = r[s].y & 0xffff0000u;
-        hi.x = r[s].z << 16;
-        hi.y = r[s].z & 0xffff0000u;
-        hi.z = r[s].w << 16;
-        hi.w = r[s].w & 0xffff0000u;
-        *(u4*)(S + kk * FLDP + 8 * m8) = lo;
-        *(u4*)(S + kk * FLDP + 8 * m8 + 4) = hi;
-      }
+    for (int s = 0; s < NL; ++s) {
+      const int idx = t + 256 * s, kk = idx >> 5, m4 = idx & 31;
+      *(f4*)(sA + buf * FBK * FLDP + kk * FLDP + 4 * m4) = ra[s];
+      *(f4*)(sB + buf * FBK * FLDP + kk * FLDP + 4 * m4) = rb[s];
     }
   };
-  v4f acc[4][4];
+  v16f acc[2][2];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
   auto compute = [&](int cur) {
-    const float* sa = sA + cur * FBK * FLDP + wr * 64 + (lane & 15);
-    const float* sb = sB + cur * FBK * FLDP + wc * 64 + (lane & 15);
+    const float* sa = sA + cur * FBK * FLDP + wr * 64 + (lane & 31);
+    const float* sb = sB + cur * FBK * FLDP + wc * 64 + (lane & 31);
 #pragma unroll
-    for (int kk = 0; kk < FBK; kk += 4) {
-      const int ko = (kk + (lane >> 4)) * FLDP;
-      float af[4], bf[4];
+    for (int kk = 0; kk < FBK; kk += 2) {
+      const int ko = (kk + (lane >> 5)) * FLDP;
+      float af[2], bf[2];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) af[x] = sa[ko + 16 * x];
+      for (int x = 0; x < 2; ++x) af[x] = sa[ko + 32 * x];
 #pragma unroll
-      for (int y = 0; y < 4; ++y) bf[y] = sb[ko + 16 * y];
+      for (int y = 0; y < 2; ++y) bf[y] = sb[ko + 32 * y];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = mfma32(bf[y], af[x], acc[x][y]);
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma32x32(bf[y], af[x], acc[x][y]);
     }
   };
-  const int ra = u * BLK, rb = v * BLK;
+  // global loads run two stages ahead of the MFMAs (two register sets)
   const int nst = (int)(ts / FBK);  // even
-  gl(A, abf, ra, 0, ra0);
-  gl(B, bbf, rb, 0, rb0);
-  gl(A, abf, ra, FBK, ra1);
-  gl(B, bbf, rb, FBK, rb1);
-  st(sA, abf, ra0);
-  st(sB, bbf, rb0);
+  gload(0, ra0, rb0);
+  gload(FBK, ra1, rb1);
+  sstore(0, ra0, rb0);
   __syncthreads();
   for (int s = 0; s < nst; s += 2) {
-    if (s + 2 < nst) {
-      gl(A, abf, ra, (s + 2) * FBK, ra0);
-      gl(B, bbf, rb, (s + 2) * FBK, rb0);
-    }
+    if (s + 2 < nst) gload((s + 2) * FBK, ra0, rb0);
     compute(0);
-    st(sA + FBK * FLDP, abf, ra1);
-    st(sB + FBK * FLDP, bbf, rb1);
+    sstore(1, ra1, rb1);
     __syncthreads();
-    if (s + 3 < nst) {
-      gl(A, abf, ra, (s + 3) * FBK, ra1);
-      gl(B, bbf, rb, (s + 3) * FBK, rb1);
-    }
+    if (s + 3 < nst) gload((s + 3) * FBK, ra1, rb1);
     compute(1);
-    if (s + 2 < nst) {
-      st(sA, abf, ra0);
-      st(sB, bbf, rb0);
-    }
+    if (s + 2 < nst) sstore(0, ra0, rb0);
     __syncthreads();
   }
-  // C(m, n) -= acc: m = wr*64 + 16x + (lane & 15), n = wc*64 + 16y + 4 (lane >> 4) + r
+  // C(m, n) -= acc: m = wr*64 + 32x + lane % 32, n = wc*64 + 32y + 8 (r/4) + 4 (lane/32) + r % 4
+  const int64_t ic = off_index(i, j, M.NT);
+  const bool cbf = tag[ic] != 0;
   float* C = (float*)M.off + ic * tt + u * BLK + (int64_t)v * BLK * ts;
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int m = wr * 64 + 16 * x + (lane & 15);
+  for (int x = 0; x < 2; ++x) {
+    const int m = wr * 64 + 32 * x + (lane & 31);
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int n = wc * 64 + 16 * y + 4 * (lane >> 4) + r;
+      for (int r = 0; r < 16; ++r) {
+        const int n = wc * 64 + 32 * y + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int64_t o = m + (int64_t)n * ts;
         if (!cbf) {
           C[o] -= acc[x][y][r];
@@ -291,19 +264,30 @@ void launch_panel_gather(const TileMat& M, int64_t k, const uint8_t* tag, double
   hipLaunchKernelGGL(k_panel_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, k, tag, pbuf, count);
 }
 
-void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const double* pbuf, hipStream_t s) {
+void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const double* pbuf, float* p32,
+                          hipStream_t s) {
   const int64_t count = M.NT - k - 1;
   if (count <= 0) return;
   const int64_t n = count * M.ts * M.ts;
-  hipLaunchKernelGGL(k_panel_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, k, tag, pbuf, count);
+  hipLaunchKernelGGL(k_panel_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, k, tag, pbuf, p32,
+                     count);
 }
 
-void launch_update_lp(const TileMat& M, const uint8_t* tag, int64_t k, int64_t nreal, hipStream_t s) {
+void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, int64_t k, int64_t nreal, int part,
+                      hipStream_t s) {
   const int T = (int)(M.ts / BLK);
   const int64_t m = M.NT - k - 2;  // strictly-lower pairs among the m + 1 trailing tiles
   if (m <= 0) return;
-  const int64_t nblk = m * (m + 1) / 2 * T * T;
-  hipLaunchKernelGGL(k_update_lp, dim3((unsigned)nblk), dim3(256), 0, s, M, tag, T, k, nreal, nblk);
+  int mode = PAIRS_TRI;
+  int64_t off = 0, npairs = m * (m + 1) / 2;
+  if (part == UPD_FIRST_COLUMN) {
+    mode = PAIRS_COL, npairs = m;
+  } else if (part == UPD_REST) {
+    off = 1, npairs = (m - 1) * m / 2;
+  }
+  if (npairs <= 0) return;
+  const int64_t nblk = npairs * T * T;
+  hipLaunchKernelGGL(k_update_lp, dim3((unsigned)nblk), dim3(256), 0, s, M, tag, p32, T, k, nreal, nblk, mode, off);
 }
 
 void launch_trsv_fwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, int64_t nreal, double* rhs,

@@ -159,8 +159,11 @@ __global__ void k_scatter(const double* __restrict__ v, const int32_t* __restric
 __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64_t lda, double* __restrict__ dinv,
                                                    double* __restrict__ ldpart, unsigned long long* __restrict__ info,
                                                    int64_t col0) {
-  __shared__ double Ls[BLK * BLK];  // L, column-major
-  __shared__ double pub[2][BLK];    // published column (factor) / row (inverse)
+  // L packed by columns (lower triangle only): L_rc at lcol(c) + r - c.  The
+  // block needs 69 KB of LDS, so it fits on a CU beside one trailing-update
+  // block and the lookahead panel is not starved by the update.
+  __shared__ double Ls[BLK * (BLK + 1) / 2];
+  __shared__ double pub[2][BLK];  // published column (factor) / row (inverse)
   __shared__ double dg[BLK];
   const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
   double a[8][8];
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64
     for (int q = 0; q < 8; ++q) {
       const int r = tr + 16 * p, c = tc + 16 * q;
       const double lv = (r >= c) ? a[p][q] : 0.0;
-      Ls[c * BLK + r] = lv;
+      if (r >= c) Ls[c * BLK - c * (c - 1) / 2 + r - c] = lv;
       A[r + (int64_t)c * lda] = lv;
       a[p][q] = 0.0;  // now T, strictly lower part
     }
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64
 #pragma unroll
       for (int p = pm; p < 8; ++p) {
         const int r = tr + 16 * p;
-        li[p] = (r > m) ? Ls[m * BLK + r] * inv_lmm : 0.0;
+        li[p] = (r > m) ? Ls[m * BLK - m * (m - 1) / 2 + r - m] * inv_lmm : 0.0;
       }
 #pragma unroll
       for (int q = 0; q <= pm; ++q) {

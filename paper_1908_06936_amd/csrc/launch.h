@@ -42,13 +42,17 @@ void launch_diag_apply_n(const double* Xk, int64_t ts, const double* b, double* 
 void launch_tile_bbox(const double* xs, const double* ys, int64_t ts, int64_t NT, int64_t nreal, double* box,
                       hipStream_t s);
 void launch_panel_gather(const TileMat& M, int64_t k, const uint8_t* tag, double* pbuf, hipStream_t s);
-void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const double* pbuf, hipStream_t s);
-void launch_update_lp(const TileMat& M, const uint8_t* tag, int64_t k, int64_t nreal, hipStream_t s);
+void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const double* pbuf, float* p32,
+                          hipStream_t s);
+void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, int64_t k, int64_t nreal, int part,
+                      hipStream_t s);
 void launch_trsv_fwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, int64_t nreal, double* rhs,
                         double* y, hipStream_t s);
 
 // k_gemm.hip
-void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, bool diag_only,
+// trailing update of step k (diag_only: only the diagonal targets); part is
+// an UpdatePart: all targets, the first trailing column, or the rest
+void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, bool diag_only, int part,
                         hipStream_t s);
 void launch_panel(double* Dk, double* below, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k,
                   double* ldpart_k, unsigned long long* info, hipStream_t s);
