@@ -127,7 +127,9 @@ exageo_status exageo_loglik(exageo_ctx *ctx, int64_t n, const double *x, const d
                             const double theta[3], int precision, double *loglik, int64_t *info);
 
 /* l(theta) and grad[k] = dl/dtheta_k for theta = (sigma2, beta, nu).
- * On ENOTPD grad is left untouched. */
+ * EXAGEO_MIXED computes the inverse factor and Sigma^-1 on FP32 MFMA (FP64
+ * diagonal tiles, FP32 off-diagonal tiles) after the mixed factorisation; the
+ * score sums stay FP64.  On ENOTPD grad is left untouched. */
 exageo_status exageo_loglik_grad(exageo_ctx *ctx, int64_t n, const double *x, const double *y,
                                  const double *z, const double theta[3], int precision, double *loglik,
                                  double grad[3], int64_t *info);

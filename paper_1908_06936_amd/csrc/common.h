@@ -2,8 +2,10 @@
 //
 // Layout conventions
 //   * The n x n covariance is padded to npad = NT * ts and stored as its lower
-//     tiles only: tile (i, j), i >= j, is a ts x ts column-major block
-//     (leading dimension ts) at element offset ((i (i + 1) / 2) + j) ts^2.
+//     tiles only, each a ts x ts column-major block (leading dimension ts):
+//     the NT diagonal tiles in one FP64 array (tile k at k ts^2), the
+//     off-diagonal tiles (i, j), i > j, column by column in a second array
+//     (slot off_index(i, j) ts^2; FP64, or 4-byte slots in mixed precision).
 //     Padding: Sigma_pp = 1 on padded diagonal entries, 0 elsewhere, which
 //     adds nothing to log det Sigma or to z^T Sigma^-1 z (padded z = 0).
 //   * Every dense product is cut into 128 x 128 output blocks, one per
@@ -12,6 +14,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace exg {
 
@@ -23,6 +27,24 @@ constexpr int GEMM_LDS = 2 * 2 * BK * LDP;  // doubles: 2 operands x 2 stages
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+
+// two consecutive operand elements held between the global load and the LDS
+// store of the FP64 core; FP32 sources are widened (exactly) at the store
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> {
+  d2 v;
+  __device__ __forceinline__ void load(const double* p) { v = *(const d2*)p; }
+  __device__ __forceinline__ d2 get() const { return v; }
+};
+template <>
+struct Pair2<float> {
+  fl2 v;
+  __device__ __forceinline__ void load(const float* p) { v = *(const fl2*)p; }
+  __device__ __forceinline__ d2 get() const { return (d2){(double)v.x, (double)v.y}; }
+};
 
 __device__ __forceinline__ int64_t tri(int64_t i) { return i * (i + 1) / 2; }
 
@@ -96,8 +118,9 @@ __device__ __forceinline__ v4d mfma64(double x, double y, v4d c) {
 //     Aop(m, k0 + q) = aptr(k0)[m + q * lda]   (AKC = false, m contiguous)
 //                    = aptr(k0)[q + m * lda]   (AKC = true,  k contiguous)
 //   bptr / Bop(n, k) likewise with ldb, BKC.
-// K must be a multiple of 2 BK; every pair of doubles read must be 16-byte
-// aligned.  acc[i][j] holds output rows m = wr*64 + 16 i + (lane & 15) and
+// The operands may be FP64 or FP32 (aptr / bptr return const double* or
+// const float*; FP32 values are widened exactly).  K must be a multiple of
+// 2 BK; every pair of elements read must be aligned to its size.  acc[i][j] holds output rows m = wr*64 + 16 i + (lane & 15) and
 // columns n = wc*64 + 16 j + 4 r + (lane >> 4), r = 0..3 (wr = wave >> 1,
 // wc = wave & 1); with this assignment the lanes of one store instruction
 // write 16 consecutive rows of a column-major output.
@@ -108,51 +131,55 @@ __device__ __forceinline__ void gemm_core(AP aptr, int64_t lda, BP bptr, int64_t
   const int wr = w >> 1, wc = w & 1;
   double* sA = sm;
   double* sB = sm + 2 * BK * LDP;
+  using TA = std::remove_cv_t<std::remove_pointer_t<decltype(aptr(0))>>;
+  using TB = std::remove_cv_t<std::remove_pointer_t<decltype(bptr(0))>>;
   // two register sets: the global loads run two stages ahead of the MFMAs
-  d2 ra0[4], rb0[4], ra1[4], rb1[4];
-  auto gload = [&](int k0, d2 (&ra)[4], d2 (&rb)[4]) {
-    const double* A = aptr(k0);
-    const double* B = bptr(k0);
+  Pair2<TA> ra0[4], ra1[4];
+  Pair2<TB> rb0[4], rb1[4];
+  auto gload = [&](int k0, Pair2<TA> (&ra)[4], Pair2<TB> (&rb)[4]) {
+    const TA* A = aptr(k0);
+    const TB* B = bptr(k0);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int idx = t + GEMM_THREADS * s;
       if (!AKC) {
         const int kk = idx >> 6, m2 = idx & 63;
-        ra[s] = *(const d2*)(A + 2 * m2 + (int64_t)kk * lda);
+        ra[s].load(A + 2 * m2 + (int64_t)kk * lda);
       } else {
         const int m = idx >> 3, kp = idx & 7;
-        ra[s] = *(const d2*)(A + 2 * kp + (int64_t)m * lda);
+        ra[s].load(A + 2 * kp + (int64_t)m * lda);
       }
       if (!BKC) {
         const int kk = idx >> 6, n2 = idx & 63;
-        rb[s] = *(const d2*)(B + 2 * n2 + (int64_t)kk * ldb);
+        rb[s].load(B + 2 * n2 + (int64_t)kk * ldb);
       } else {
         const int n = idx >> 3, kp = idx & 7;
-        rb[s] = *(const d2*)(B + 2 * kp + (int64_t)n * ldb);
+        rb[s].load(B + 2 * kp + (int64_t)n * ldb);
       }
     }
   };
-  auto sstore = [&](int buf, d2 (&ra)[4], d2 (&rb)[4]) {
+  auto sstore = [&](int buf, const Pair2<TA> (&ra)[4], const Pair2<TB> (&rb)[4]) {
     double* a = sA + buf * BK * LDP;
     double* b = sB + buf * BK * LDP;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int idx = t + GEMM_THREADS * s;
+      const d2 va = ra[s].get(), vb = rb[s].get();
       if (!AKC) {
         const int kk = idx >> 6, m2 = idx & 63;
-        *(d2*)(a + kk * LDP + 2 * m2) = ra[s];
+        *(d2*)(a + kk * LDP + 2 * m2) = va;
       } else {
         const int m = idx >> 3, kp = idx & 7;
-        a[(2 * kp) * LDP + m] = ra[s].x;
-        a[(2 * kp + 1) * LDP + m] = ra[s].y;
+        a[(2 * kp) * LDP + m] = va.x;
+        a[(2 * kp + 1) * LDP + m] = va.y;
       }
       if (!BKC) {
         const int kk = idx >> 6, n2 = idx & 63;
-        *(d2*)(b + kk * LDP + 2 * n2) = rb[s];
+        *(d2*)(b + kk * LDP + 2 * n2) = vb;
       } else {
         const int n = idx >> 3, kp = idx & 7;
-        b[(2 * kp) * LDP + n] = rb[s].x;
-        b[(2 * kp + 1) * LDP + n] = rb[s].y;
+        b[(2 * kp) * LDP + n] = vb.x;
+        b[(2 * kp + 1) * LDP + n] = vb.y;
       }
     }
   };
@@ -230,6 +257,12 @@ __device__ __forceinline__ void acc_store(double* C, int64_t ldc, const v4d (&ac
 }
 
 // Block-wide sum of NV doubles per thread in a fixed order (deterministic).
+// sum over the 64 lanes of a wave (every lane receives the total)
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* NV * blockDim */) {
   const int t = threadIdx.x, nt = blockDim.x;

@@ -64,7 +64,8 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
     p.off_tbox = take((size_t)p.NT * 4 * 8);
   }
   p.off_xd = take((size_t)p.NT * tt * 8);
-  p.off_ptmp = p.grad ? take((size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8) : 0;
+  // FP64 inverse: FP64 staging buffer (the mixed inverse stages in the FP32 panel copy)
+  p.off_ptmp = p.grad && !p.mixed ? take((size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8) : 0;
   p.off_dinv = take((size_t)p.NT * p.T * BLKH * BLKH * 8);
   p.off_ld = take((size_t)p.NT * p.T * 8);
   p.off_xs = take((size_t)p.npad * 8);
@@ -363,12 +364,24 @@ exageo_status gradient(exageo_ctx* c, const Plan& p) {
   double* Xd = at<double>(c, p.off_xd);
   // a = Sigma^-1 z = L^-T y
   exg::launch_copy(rhs, at<double>(c, p.off_y), p.npad, c->stream);
-  exg::launch_trsv_bwd(M, false, Xd, rhs, av, c->stream);
-  // L^-1 in place, then the fused LAUUM + contraction
-  for (int64_t k = 0; k < p.NT; ++k)
-    exg::launch_trtri_step(M, Xd + k * p.ts * p.ts, at<double>(c, p.off_ptmp), k, p.n, c->stream);
-  exg::launch_lauum_contract(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
-                             at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part), c->stream);
+  if (p.mixed) {
+    // mixed precision: the same steps with FP32 off-diagonal tiles of L^-1
+    const uint8_t* tag = at<uint8_t>(c, p.off_tag);
+    exg::launch_trsv_bwd_lp(M, tag, Xd, rhs, av, c->stream);
+    for (int64_t k = 0; k < p.NT; ++k)
+      exg::launch_trtri_step_lp(M, tag, Xd + k * p.ts * p.ts, at<float>(c, p.off_p32), k, p.n, c->stream);
+    exg::launch_lauum_contract_lp(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
+                                  at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part),
+                                  c->stream);
+  } else {
+    exg::launch_trsv_bwd(M, false, Xd, rhs, av, c->stream);
+    // L^-1 in place, then the fused LAUUM + contraction
+    for (int64_t k = 0; k < p.NT; ++k)
+      exg::launch_trtri_step(M, Xd + k * p.ts * p.ts, at<double>(c, p.off_ptmp), k, p.n, c->stream);
+    exg::launch_lauum_contract(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
+                               at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part),
+                               c->stream);
+  }
   exg::launch_finalize_grad(at<double>(c, p.off_part), exg::lauum_blocks(p.ts, p.NT), at<double>(c, p.off_out) + 3,
                             c->stream);
   HIPCHK(c, hipGetLastError());
@@ -583,8 +596,6 @@ static exageo_status loglik_common(exageo_ctx* c, int64_t n, const double* x, co
   if (n < 1 || !x || !y || !z || !theta_ok(theta) || !loglik || (want_grad && !grad))
     return fail(c, EXAGEO_EINVAL, "loglik: invalid argument");
   if (precision != EXAGEO_FP64 && precision != EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "unknown precision");
-  if (precision == EXAGEO_MIXED && want_grad)
-    return fail(c, EXAGEO_EINVAL, "the gradient is computed in FP64 only (precision must be EXAGEO_FP64)");
   if (n > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n too large");
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
   Plan p = make_plan(n, c->ts, want_grad, precision);
@@ -652,8 +663,6 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
     return fail(c, EXAGEO_EINVAL, "mle: invalid argument");
   if (method != EXAGEO_DFO && method != EXAGEO_LBFGSB) return fail(c, EXAGEO_EINVAL, "unknown method");
   if (precision != EXAGEO_FP64 && precision != EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "unknown precision");
-  if (precision == EXAGEO_MIXED && method == EXAGEO_LBFGSB)
-    return fail(c, EXAGEO_EINVAL, "the gradient method runs in FP64 only");
   for (int k = 0; k < 3; ++k) {
     if (!theta_ok(lb) || !theta_ok(ub) || lb[k] > ub[k]) return fail(c, EXAGEO_EINVAL, "mle: bad bounds");
     if (theta0 && (!(theta0[k] >= lb[k]) || !(theta0[k] <= ub[k]))) return fail(c, EXAGEO_EINVAL, "theta0 outside bounds");

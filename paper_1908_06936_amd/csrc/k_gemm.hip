@@ -19,8 +19,8 @@
 //   (a_i a_j / 2 - W_ij / 2) dSigma_m(i, j),  a = Sigma^-1 z,
 // so W is never stored.
 #include "common.h"
+#include "contract.h"
 #include "launch.h"
-#include "matern_dev.h"
 
 namespace exg {
 
@@ -255,44 +255,7 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract(TileMat M, int T, int
     return tptr(M, K, J) + (kk % ts) + c0 * ts;
   };
   gemm_core<true, true>(ap, ts, bp, ts, (int)(L0 + (NT - 1 - I) * ts), acc, sm);
-  // epilogue: regenerate dSigma for this block's entries and contract
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  double g3[3] = {0.0, 0.0, 0.0};
-  // The 16 values of one row group go through thread-private LDS slots so
-  // that the quadrature loop below indexes them at run time without forcing
-  // the accumulator array out of registers.
-  double* fb = sm;  // 16 x 256 doubles, free after the k loop
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) fb[(j * 4 + r) * GEMM_THREADS + t] = acc[i][j][r];
-    const int64_t gi = I * ts + u * BLK + wr * 64 + 16 * i + (lane & 15);
-    if (gi >= nreal) continue;
-    const double xi = xs[gi], yi = ys[gi], ai = av[gi];
-    for (int e = 0; e < 16; ++e) {
-      const int j = e >> 2, r = e & 3;
-      const int64_t gj = J * ts + v * BLK + wc * 64 + 16 * j + 4 * r + (lane >> 4);
-      if (gj >= nreal || gj > gi) continue;
-      const double wgt = (gi == gj) ? 0.5 : 1.0;  // (w / 2) with w = 1 or 2
-      const double f = wgt * (ai * av[gj] - fb[e * GEMM_THREADS + t]);
-      const double dx = xi - xs[gj], dy = yi - ys[gj];
-      double d0, d1, d2;
-      matern_grad(sqrt(dx * dx + dy * dy), cst, qt, &d0, &d1, &d2);
-      g3[0] += f * d0;
-      g3[1] += f * d1;
-      g3[2] += f * d2;
-    }
-  }
-  __syncthreads();
-  block_sum<3>(g3, sm);
-  if (t == 0) {
-    part[3 * b] = g3[0];
-    part[3 * b + 1] = g3[1];
-    part[3 * b + 2] = g3[2];
-  }
+  contract_block64(acc, I * ts + r0, J * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
 }
 
 // ------------------------------------------------------------- launchers

@@ -18,18 +18,57 @@
 #include <float.h>
 
 #include "common.h"
+#include "contract.h"
+#include "gemm32.h"
 #include "launch.h"
 
 namespace exg {
 
 
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return bf16_bits_to_f32(h); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) { return f32_to_bf16_rne(f); }
 
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// C(m, n) += alpha acc over one 128 x 128 block of the off-diagonal tile
+// whose slot starts at `tile` (in-tile element offset o0 of the block's first
+// entry, leading dimension ld): FP32 tiles in place, BF16 tiles (first half of
+// the slot) widened, updated and rounded to nearest even.
+__device__ __forceinline__ void acc32_update(void* tile, bool bf, int64_t o0, int64_t ld, const v16f (&acc)[2][2],
+                                             float alpha) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    const int m = wr * 64 + 32 * x + (lane & 31);
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = wc * 64 + 32 * y + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t o = o0 + m + (int64_t)n * ld;
+        if (!bf) {
+          float* C = (float*)tile;
+          C[o] += alpha * acc[x][y][r];
+        } else {
+          uint16_t* Ch = (uint16_t*)tile;
+          Ch[o] = f32_to_bf16(bf16_to_f32(Ch[o]) + alpha * acc[x][y][r]);
+        }
+      }
+  }
+}
+
+// C(m, n) = alpha acc into a 128 x 128 block of an FP32 array
+__device__ __forceinline__ void acc32_store(float* C, int64_t ld, const v16f (&acc)[2][2], float alpha) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    const int m = wr * 64 + 32 * x + (lane & 31);
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = wc * 64 + 32 * y + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        C[m + (int64_t)n * ld] = alpha * acc[x][y][r];
+      }
+  }
 }
 
 __device__ __forceinline__ float* off32(const TileMat& M, int64_t i, int64_t j) {
@@ -101,28 +140,15 @@ __global__ void k_panel_scatter(TileMat M, int64_t k, const uint8_t* __restrict_
 }
 
 // ------------------------------------------------ FP32 MFMA trailing update
-constexpr int FBK = 16;        // k-depth of one LDS stage
-constexpr int FLDP = BLK + 4;  // padded LDS row (floats)
-constexpr int FLDS = 2 * 2 * FBK * FLDP;
-
-typedef float v16f __attribute__((ext_vector_type(16)));
-
-__device__ __forceinline__ v16f mfma32x32(float x, float y, v16f c) {
-  return __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, c, 0, 0, 0);
-}
-
 // C_ij -= L_ik L_jk^T for the off-diagonal targets k < j < i < NT, with the
 // operands taken from the FP32 rounding of the FP64 panel (p32 tile q holds
 // L_{k+1+q, k}), so that a BF16-stored panel tile never feeds its rounding
 // error into targets near the diagonal.  One 256-thread block computes one
-// 128 x 128 block of a target tile; wave (wr, wc) owns its 64 x 64 quarter as
-// 2 x 2 products on v_mfma_f32_32x32x2f32.  That instruction takes operand X
-// lane l as X[l % 32][l / 32] and Y lane l as Y[l / 32][l % 32]; D = X Y has
-// lane l, register r at D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+// 128 x 128 block of a target tile.
 __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* __restrict__ tag,
                                                       const float* __restrict__ p32, int T, int64_t k,
                                                       int64_t nreal, int64_t nb, int mode, int64_t off) {
-  __shared__ float sm[FLDS];
+  __shared__ float sm[G32_LDS];
   const int64_t ts = M.ts, tt = ts * ts;
   const int64_t b = blockIdx.x;
   if (b >= nb) return;
@@ -133,91 +159,12 @@ __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* 
   pair_map(mode, off, p, &a, &c);  // c <= a
   const int64_t i = k + 2 + a, j = k + 1 + c;
   if (i * ts + u * BLK >= nreal) return;  // padded rows: update is zero
-  const float* A = p32 + (a + 1) * tt + u * BLK;
-  const float* B = p32 + c * tt + v * BLK;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  constexpr int NL = FBK * BLK / 4 / 256;  // float4 loads per thread per operand and stage
-  f4 ra0[NL], rb0[NL], ra1[NL], rb1[NL];
-  float* sA = sm;
-  float* sB = sm + 2 * FBK * FLDP;
-  auto gload = [&](int k0, f4 (&ra)[NL], f4 (&rb)[NL]) {
-#pragma unroll
-    for (int s = 0; s < NL; ++s) {
-      const int idx = t + 256 * s, kk = idx >> 5, m4 = idx & 31;
-      ra[s] = *(const f4*)(A + 4 * m4 + (int64_t)(k0 + kk) * ts);
-      rb[s] = *(const f4*)(B + 4 * m4 + (int64_t)(k0 + kk) * ts);
-    }
-  };
-  auto sstore = [&](int buf, f4 (&ra)[NL], f4 (&rb)[NL]) {
-#pragma unroll
-    for (int s = 0; s < NL; ++s) {
-      const int idx = t + 256 * s, kk = idx >> 5, m4 = idx & 31;
-      *(f4*)(sA + buf * FBK * FLDP + kk * FLDP + 4 * m4) = ra[s];
-      *(f4*)(sB + buf * FBK * FLDP + kk * FLDP + 4 * m4) = rb[s];
-    }
-  };
   v16f acc[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
-  auto compute = [&](int cur) {
-    const float* sa = sA + cur * FBK * FLDP + wr * 64 + (lane & 31);
-    const float* sb = sB + cur * FBK * FLDP + wc * 64 + (lane & 31);
-#pragma unroll
-    for (int kk = 0; kk < FBK; kk += 2) {
-      const int ko = (kk + (lane >> 5)) * FLDP;
-      float af[2], bf[2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x) af[x] = sa[ko + 32 * x];
-#pragma unroll
-      for (int y = 0; y < 2; ++y) bf[y] = sb[ko + 32 * y];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = mfma32x32(bf[y], af[x], acc[x][y]);
-    }
-  };
-  // global loads run two stages ahead of the MFMAs (two register sets)
-  const int nst = (int)(ts / FBK);  // even
-  gload(0, ra0, rb0);
-  gload(FBK, ra1, rb1);
-  sstore(0, ra0, rb0);
-  __syncthreads();
-  for (int s = 0; s < nst; s += 2) {
-    if (s + 2 < nst) gload((s + 2) * FBK, ra0, rb0);
-    compute(0);
-    sstore(1, ra1, rb1);
-    __syncthreads();
-    if (s + 3 < nst) gload((s + 3) * FBK, ra1, rb1);
-    compute(1);
-    if (s + 2 < nst) sstore(0, ra0, rb0);
-    __syncthreads();
-  }
-  // C(m, n) -= acc: m = wr*64 + 32x + lane % 32, n = wc*64 + 32y + 8 (r/4) + 4 (lane/32) + r % 4
+  acc32_zero(acc);
+  gemm32_blk<SRC_F32, false, SRC_F32, false>(p32 + (a + 1) * tt + u * BLK, ts, p32 + c * tt + v * BLK, ts, (int)ts,
+                                              acc, sm);
   const int64_t ic = off_index(i, j, M.NT);
-  const bool cbf = tag[ic] != 0;
-  float* C = (float*)M.off + ic * tt + u * BLK + (int64_t)v * BLK * ts;
-#pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    const int m = wr * 64 + 32 * x + (lane & 31);
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int n = wc * 64 + 32 * y + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t o = m + (int64_t)n * ts;
-        if (!cbf) {
-          C[o] -= acc[x][y][r];
-        } else {
-          uint16_t* Ch = (uint16_t*)C;
-          Ch[o] = f32_to_bf16(bf16_to_f32(Ch[o]) - acc[x][y][r]);
-        }
-      }
-  }
+  acc32_update((float*)M.off + ic * tt, tag[ic] != 0, u * BLK + (int64_t)v * BLK * ts, ts, acc, -1.f);
 }
 
 // ------------------------------------------------- solves on mixed tiles
@@ -249,6 +196,191 @@ __global__ __launch_bounds__(256) void k_gemv_fwd_lp(TileMat M, const uint8_t* _
   red[t] = s;
   __syncthreads();
   if (h == 0) rhs[i * ts + u * BLK + r] -= red[r] + red[r + 128];
+}
+
+// rhs_j -= L_kj^T a_k over the 128-column blocks of the tiles j < k (one block
+// per workgroup), reading FP32 or BF16 tiles and accumulating in FP64
+__global__ __launch_bounds__(256) void k_gemv_bwd_lp(TileMat M, const uint8_t* __restrict__ tag, int64_t k,
+                                                     const double* __restrict__ ak, double* __restrict__ rhs) {
+  const int64_t ts = M.ts;
+  const int T = (int)(ts / BLK);
+  const int64_t cb = blockIdx.x;
+  const int64_t j = cb / T;
+  const int v = (int)(cb % T);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t idx = off_index(k, j, M.NT);
+  const float* L = (const float*)M.off + idx * ts * ts;
+  const bool bf = tag[idx] != 0;
+  for (int n = w; n < BLK; n += 4) {
+    const int64_t col = (int64_t)v * BLK + n;
+    double s = 0.0;
+    if (bf) {
+      const uint16_t* Lc = (const uint16_t*)L + col * ts;
+      for (int64_t r = lane; r < ts; r += 64) s += (double)bf16_to_f32(Lc[r]) * ak[r];
+    } else {
+      const float* Lc = L + col * ts;
+      for (int64_t r = lane; r < ts; r += 64) s += (double)Lc[r] * ak[r];
+    }
+    s = wave_sum(s);
+    if (lane == 0) rhs[j * ts + col] -= s;
+  }
+}
+
+// ------------------------------------------------ mixed tile TRTRI, step k
+// The same four steps as the FP64 inverse, with every off-diagonal tile of
+// L^-1 held in FP32 (the 4-byte slots take FP32 whatever the tile's tag was:
+// a tile is read through its tag only as an untouched factor tile, in the
+// first step below, and is FP32 from then on) and every product on FP32 MFMA.
+// P_i = -L_ik X_kk for i > k into the FP32 buffer P (tile i - k - 1); k range
+// restricted to the non-zero rows v*128.. of the lower-triangular X_kk.
+__global__ __launch_bounds__(256, 2) void k_tri_right_lp(TileMat M, const uint8_t* __restrict__ tag,
+                                                         const double* __restrict__ Xk, float* __restrict__ P, int T,
+                                                         int64_t k, int64_t nreal, int64_t nb) {
+  __shared__ float sm[G32_LDS];
+  const int64_t ts = M.ts, tt = ts * ts;
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const int64_t i = k + 1 + b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  const int64_t off = (int64_t)v * BLK * ts;
+  float* C = P + (i - k - 1) * tt + u * BLK + off;
+  v16f acc[2][2];
+  acc32_zero(acc);
+  // padded rows of L^-1 are zero: store zeros (the buffer is copied back whole)
+  if (i * ts + u * BLK < nreal) {
+    const int64_t idx = off_index(i, k, M.NT);
+    const float* A = (const float*)M.off + idx * tt;
+    const double* B = Xk + v * BLK + off;
+    const int K = (int)(ts - v * BLK);
+    if (tag[idx])
+      gemm32_blk<SRC_BF16, false, SRC_F64, true>((const uint16_t*)A + u * BLK + off, ts, B, ts, K, acc, sm);
+    else
+      gemm32_blk<SRC_F32, false, SRC_F64, true>(A + u * BLK + off, ts, B, ts, K, acc, sm);
+  }
+  acc32_store(C, ts, acc, -1.f);
+}
+
+// A_ij += P_i A_kj for k < i < NT, 0 <= j < k (P_i = the new A_ik)
+__global__ __launch_bounds__(256, 2) void k_tri_gemm_lp(TileMat M, const float* __restrict__ P, int T, int64_t k,
+                                                        int64_t nreal, int64_t nb) {
+  __shared__ float sm[G32_LDS];
+  const int64_t ts = M.ts, tt = ts * ts;
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const int64_t p = b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  const int64_t i = k + 1 + p / k, j = p % k;
+  if (i * ts + u * BLK >= nreal) return;
+  v16f acc[2][2];
+  acc32_zero(acc);
+  gemm32_blk<SRC_F32, false, SRC_F32, true>(P + (i - k - 1) * tt + u * BLK, ts, off32(M, k, j) + (int64_t)v * BLK * ts,
+                                            ts, (int)ts, acc, sm);
+  acc32_update(off32(M, i, j), false, u * BLK + (int64_t)v * BLK * ts, ts, acc, 1.f);
+}
+
+// R_j = X_kk A_kj for j < k into the FP32 buffer P (tile j); k range
+// restricted to the non-zero columns ..(u+1)*128 of row block u of X_kk.
+__global__ __launch_bounds__(256, 2) void k_tri_left_lp(TileMat M, const double* __restrict__ Xk,
+                                                        float* __restrict__ P, int T, int64_t k, int64_t nb) {
+  __shared__ float sm[G32_LDS];
+  const int64_t ts = M.ts, tt = ts * ts;
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const int64_t j = b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  const int64_t off = (int64_t)v * BLK * ts;
+  v16f acc[2][2];
+  acc32_zero(acc);
+  gemm32_blk<SRC_F64, false, SRC_F32, true>(Xk + u * BLK, ts, off32(M, k, j) + off, ts, (u + 1) * BLK, acc, sm);
+  acc32_store(P + j * tt + u * BLK + off, ts, acc, 1.f);
+}
+
+// FP32 tile (i0 + q, jcol) or (irow, j0 + q) <- P tile q, q < count
+__global__ void k_copy_back_lp(TileMat M, const float* __restrict__ P, int64_t count, int64_t i0, int64_t j0,
+                               int column) {
+  const int64_t tt = M.ts * M.ts;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count * tt) return;
+  const int64_t q = e / tt, o = e % tt;
+  const int64_t i = column ? i0 + q : i0, j = column ? j0 : j0 + q;
+  off32(M, i, j)[o] = P[e];
+}
+
+// ------------------------------------ mixed fused LAUUM + score contraction
+// X = L^-1 has FP64 diagonal tiles and FP32 off-diagonal tiles.  Off-diagonal
+// blocks W_IJ (I > J) run on FP32 MFMA with FP32 accumulation; diagonal
+// blocks W_II on FP64 MFMA (FP32 tiles widened exactly), so that the
+// precision map of W is that of Sigma.  The contraction is FP64 in both.
+// Off-diagonal kernel: pair p -> (a, c), c <= a, I = a + 1 > J = c.
+__global__ __launch_bounds__(256, 2) void k_lauum_contract_lp(TileMat M, int T, int64_t nreal,
+                                                              const double* __restrict__ xs,
+                                                              const double* __restrict__ ys,
+                                                              const double* __restrict__ av,
+                                                              const double* __restrict__ qt,
+                                                              const double* __restrict__ cst,
+                                                              double* __restrict__ part, int64_t nb) {
+  __shared__ float sm[G32_LDS];
+  const int64_t ts = M.ts, NT = M.NT;
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const int64_t p = b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  int64_t a, c;
+  tri_decode(p, &a, &c);
+  const int64_t I = a + 1, J = c;
+  if (I * ts + u * BLK >= nreal || J * ts + v * BLK >= nreal) {
+    if (threadIdx.x < 3) part[3 * b + threadIdx.x] = 0.0;
+    return;
+  }
+  v16f acc[2][2];
+  acc32_zero(acc);
+  const int64_t r0 = (int64_t)u * BLK, c0 = (int64_t)v * BLK;
+  // K = I: rows r0.. of the lower-triangular X_II against the same rows of X_IJ
+  gemm32_blk<SRC_F64, true, SRC_F32, true>(M.diag + I * ts * ts + r0 + r0 * ts, ts, off32(M, I, J) + r0 + c0 * ts, ts,
+                                           (int)(ts - r0), acc, sm);
+  // K = I + 1 .. NT - 1: every row of the tiles below
+  if (I + 1 < NT) {
+    auto ap = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, I) + (k0 % ts) + r0 * ts; };
+    auto bp = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, J) + (k0 % ts) + c0 * ts; };
+    gemm32<SRC_F32, true, SRC_F32, true>(ap, ts, bp, ts, (int)((NT - 1 - I) * ts), acc, sm);
+  }
+  contract_block32(acc, I * ts + r0, J * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
+}
+
+// Diagonal kernel: block (I, I, u, v), v <= u, on FP64 MFMA.
+__global__ __launch_bounds__(256, 2) void k_lauum_diag_lp(TileMat M, int T, int64_t nreal,
+                                                          const double* __restrict__ xs,
+                                                          const double* __restrict__ ys,
+                                                          const double* __restrict__ av,
+                                                          const double* __restrict__ qt,
+                                                          const double* __restrict__ cst, double* __restrict__ part,
+                                                          int64_t nb) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t ts = M.ts, NT = M.NT;
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const int64_t I = b / (T * T);
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  if (u < v || I * ts + u * BLK >= nreal || I * ts + v * BLK >= nreal) {
+    if (threadIdx.x < 3) part[3 * b + threadIdx.x] = 0.0;
+    return;
+  }
+  v4d acc[4][4];
+  acc_zero(acc);
+  const int64_t r0 = (int64_t)u * BLK, c0 = (int64_t)v * BLK;
+  const double* XII = M.diag + I * ts * ts;
+  gemm_blk<true, true>(XII + r0 + r0 * ts, ts, XII + r0 + c0 * ts, ts, (int)(ts - r0), acc, sm);
+  if (I + 1 < NT) {
+    auto ap = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, I) + (k0 % ts) + r0 * ts; };
+    auto bp = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, I) + (k0 % ts) + c0 * ts; };
+    gemm_core<true, true>(ap, ts, bp, ts, (int)((NT - 1 - I) * ts), acc, sm);
+  }
+  contract_block64(acc, I * ts + r0, I * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -303,6 +435,52 @@ void launch_trsv_fwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, 
       hipLaunchKernelGGL(k_gemv_fwd_lp, dim3((unsigned)(gmax - g0)), dim3(256), shm, s, M, tag, k, g0, y + k * ts,
                          rhs);
   }
+}
+
+void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, double* rhs, double* a,
+                        hipStream_t s) {
+  const int64_t ts = M.ts, NT = M.NT;
+  const int T = (int)(ts / BLK);
+  for (int64_t k = NT - 1; k >= 0; --k) {
+    launch_diag_apply_t(Xd + k * ts * ts, ts, rhs + k * ts, a + k * ts, s);
+    if (k > 0)
+      hipLaunchKernelGGL(k_gemv_bwd_lp, dim3((unsigned)(k * T)), dim3(256), 0, s, M, tag, k, a + k * ts, rhs);
+  }
+}
+
+void launch_trtri_step_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k, int64_t nreal,
+                          hipStream_t s) {
+  const int64_t ts = M.ts, NT = M.NT;
+  const int T = (int)(ts / BLK);
+  const int64_t tt = ts * ts;
+  const int64_t nbelow = NT - k - 1;
+  if (nbelow > 0) {
+    const int64_t nr = nbelow * T * T, ng = nbelow * k * T * T;
+    hipLaunchKernelGGL(k_tri_right_lp, dim3((unsigned)nr), dim3(256), 0, s, M, tag, Xk, P, T, k, nreal, nr);
+    if (k > 0) hipLaunchKernelGGL(k_tri_gemm_lp, dim3((unsigned)ng), dim3(256), 0, s, M, P, T, k, nreal, ng);
+    hipLaunchKernelGGL(k_copy_back_lp, dim3((unsigned)((nbelow * tt + 255) / 256)), dim3(256), 0, s, M, P, nbelow,
+                       k + 1, k, 1);
+  }
+  if (k > 0) {
+    const int64_t nl = k * T * T;
+    hipLaunchKernelGGL(k_tri_left_lp, dim3((unsigned)nl), dim3(256), 0, s, M, Xk, P, T, k, nl);
+    hipLaunchKernelGGL(k_copy_back_lp, dim3((unsigned)((k * tt + 255) / 256)), dim3(256), 0, s, M, P, k, k,
+                       (int64_t)0, 0);
+  }
+  launch_copy(M.diag + k * tt, Xk, tt, s);
+}
+
+// part: lauum_blocks(ts, NT) triples, the off-diagonal blocks first
+void launch_lauum_contract_lp(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* av,
+                              const double* qt, const double* cst, double* part, hipStream_t s) {
+  const int T = (int)(M.ts / BLK);
+  const int64_t NT = M.NT;
+  const int64_t nb_off = NT * (NT - 1) / 2 * T * T, nb_diag = NT * T * T;
+  if (nb_off > 0)
+    hipLaunchKernelGGL(k_lauum_contract_lp, dim3((unsigned)nb_off), dim3(256), 0, s, M, T, nreal, xs, ys, av, qt, cst,
+                       part, nb_off);
+  hipLaunchKernelGGL(k_lauum_diag_lp, dim3((unsigned)nb_diag), dim3(256), 0, s, M, T, nreal, xs, ys, av, qt, cst,
+                     part + 3 * nb_off, nb_diag);
 }
 
 }  // namespace exg

@@ -328,11 +328,6 @@ __global__ __launch_bounds__(256) void k_diag_apply_n(const double* __restrict__
   if (h == 0) out[rb * BLK + r] = red[r] + red[r + 128];
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // out = X^T b on one diagonal tile, X lower triangular; one 128-column block
 // per workgroup, one wave per column (lanes run down the column)
 __global__ __launch_bounds__(256) void k_diag_apply_t(const double* __restrict__ X, int64_t ts,
@@ -513,6 +508,10 @@ void launch_trsv_fwd(const TileMat& M, bool off32, const double* Xd, int64_t nre
 
 void launch_diag_apply_n(const double* Xk, int64_t ts, const double* b, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_diag_apply_n, dim3((unsigned)(ts / BLK)), dim3(256), 0, s, Xk, ts, b, out);
+}
+
+void launch_diag_apply_t(const double* Xk, int64_t ts, const double* b, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_apply_t, dim3((unsigned)(ts / BLK)), dim3(256), 0, s, Xk, ts, b, out);
 }
 
 void launch_trsv_bwd(const TileMat& M, bool off32, const double* Xd, double* rhs, double* a, hipStream_t s) {

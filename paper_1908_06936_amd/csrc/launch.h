@@ -37,6 +37,7 @@ void launch_copy_diag_lower(double* dst, const double* diag, int64_t ts, int64_t
 void launch_put_dinv(double* dst, const double* dinv, int64_t ts, int64_t NT, int c, hipStream_t s);
 
 void launch_diag_apply_n(const double* Xk, int64_t ts, const double* b, double* out, hipStream_t s);
+void launch_diag_apply_t(const double* Xk, int64_t ts, const double* b, double* out, hipStream_t s);
 
 // k_mixed.hip
 void launch_tile_bbox(const double* xs, const double* ys, int64_t ts, int64_t NT, int64_t nreal, double* box,
@@ -46,6 +47,13 @@ void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const
                           hipStream_t s);
 void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, int64_t k, int64_t nreal, int part,
                       hipStream_t s);
+void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, double* rhs, double* a,
+                        hipStream_t s);
+// one step of the mixed inverse (FP32 off-diagonal tiles of L^-1, FP32 buffer P)
+void launch_trtri_step_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k, int64_t nreal,
+                          hipStream_t s);
+void launch_lauum_contract_lp(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* av,
+                              const double* qt, const double* cst, double* part, hipStream_t s);
 void launch_trsv_fwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, int64_t nreal, double* rhs,
                         double* y, hipStream_t s);
 
