@@ -350,7 +350,7 @@ exageo_status solve_reduce(exageo_ctx* c, const Plan& p) {
   if (p.mixed)
     exg::launch_trsv_fwd_lp(M, at<uint8_t>(c, p.off_tag), Xd, p.n, rhs, y, c->stream);
   else
-    exg::launch_trsv_fwd(M, false, Xd, p.n, rhs, y, c->stream);
+    exg::launch_trsv_fwd(M, Xd, p.n, rhs, y, c->stream);
   exg::launch_finalize_loglik(y, p.n, at<double>(c, p.off_ld), p.NT * p.T, at<double>(c, p.off_out), c->stream);
   HIPCHK(c, hipGetLastError());
   rec(c, 4);
@@ -374,7 +374,7 @@ exageo_status gradient(exageo_ctx* c, const Plan& p) {
                                   at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part),
                                   c->stream);
   } else {
-    exg::launch_trsv_bwd(M, false, Xd, rhs, av, c->stream);
+    exg::launch_trsv_bwd(M, Xd, rhs, av, c->stream);
     // L^-1 in place, then the fused LAUUM + contraction
     for (int64_t k = 0; k < p.NT; ++k)
       exg::launch_trtri_step(M, Xd + k * p.ts * p.ts, at<double>(c, p.off_ptmp), k, p.n, c->stream);

@@ -21,6 +21,7 @@
 #include "contract.h"
 #include "gemm32.h"
 #include "launch.h"
+#include "solve.h"
 
 namespace exg {
 
@@ -168,11 +169,12 @@ __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* 
 }
 
 // ------------------------------------------------- solves on mixed tiles
-// rhs_i -= L_ik y_k for the 128-row blocks g0 <= g < gmax below tile k
-__global__ __launch_bounds__(256) void k_gemv_fwd_lp(TileMat M, const uint8_t* __restrict__ tag, int64_t k,
-                                                     int64_t g0, const double* __restrict__ yk,
-                                                     double* __restrict__ rhs) {
-  extern __shared__ double sy[];  // ts + 256
+// rhs_i -= L_ik y_k for the 128-row blocks g0 <= g < gmax below tile k,
+// reading FP32 or BF16 tiles and accumulating in FP64
+__global__ __launch_bounds__(SOLVE_THREADS) void k_gemv_fwd_lp(TileMat M, const uint8_t* __restrict__ tag, int64_t k,
+                                                              int64_t g0, const double* __restrict__ yk,
+                                                              double* __restrict__ rhs) {
+  extern __shared__ double sy[];  // ts + SOLVE_THREADS
   const int64_t ts = M.ts;
   double* red = sy + ts;
   const int T = (int)(ts / BLK);
@@ -180,49 +182,43 @@ __global__ __launch_bounds__(256) void k_gemv_fwd_lp(TileMat M, const uint8_t* _
   const int64_t i = g / T;
   const int u = (int)(g % T);
   const int t = threadIdx.x;
-  for (int q = t; q < ts; q += 256) sy[q] = yk[q];
+  for (int q = t; q < ts; q += SOLVE_THREADS) sy[q] = yk[q];
   __syncthreads();
   const int64_t idx = off_index(i, k, M.NT);
   const float* L = (const float*)M.off + idx * ts * ts;
-  const int r = t & 127, h = t >> 7;
-  double s = 0.0;
+  double s;
   if (tag[idx]) {
-    const uint16_t* Lh = (const uint16_t*)L + u * BLK + r;
-    for (int64_t q = h; q < ts; q += 2) s += (double)bf16_to_f32(Lh[q * ts]) * sy[q];
+    const uint16_t* Lh = (const uint16_t*)L + u * BLK;
+    s = slab_rowdot([=](int r, int c) { return (double)bf16_to_f32(Lh[r + (int64_t)c * ts]); }, sy, (int)ts, red);
   } else {
-    const float* Lf = L + u * BLK + r;
-    for (int64_t q = h; q < ts; q += 2) s += (double)Lf[q * ts] * sy[q];
+    const float* Lf = L + u * BLK;
+    s = slab_rowdot([=](int r, int c) { return (double)Lf[r + (int64_t)c * ts]; }, sy, (int)ts, red);
   }
-  red[t] = s;
-  __syncthreads();
-  if (h == 0) rhs[i * ts + u * BLK + r] -= red[r] + red[r + 128];
+  if (t < BLK) rhs[i * ts + u * BLK + t] -= s;
 }
 
 // rhs_j -= L_kj^T a_k over the 128-column blocks of the tiles j < k (one block
 // per workgroup), reading FP32 or BF16 tiles and accumulating in FP64
-__global__ __launch_bounds__(256) void k_gemv_bwd_lp(TileMat M, const uint8_t* __restrict__ tag, int64_t k,
-                                                     const double* __restrict__ ak, double* __restrict__ rhs) {
+__global__ __launch_bounds__(SOLVE_THREADS) void k_gemv_bwd_lp(TileMat M, const uint8_t* __restrict__ tag, int64_t k,
+                                                              const double* __restrict__ ak,
+                                                              double* __restrict__ rhs) {
   const int64_t ts = M.ts;
   const int T = (int)(ts / BLK);
   const int64_t cb = blockIdx.x;
   const int64_t j = cb / T;
-  const int v = (int)(cb % T);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t col0 = (cb % T) * BLK + 8 * (threadIdx.x >> 6);
   const int64_t idx = off_index(k, j, M.NT);
   const float* L = (const float*)M.off + idx * ts * ts;
-  const bool bf = tag[idx] != 0;
-  for (int n = w; n < BLK; n += 4) {
-    const int64_t col = (int64_t)v * BLK + n;
-    double s = 0.0;
-    if (bf) {
-      const uint16_t* Lc = (const uint16_t*)L + col * ts;
-      for (int64_t r = lane; r < ts; r += 64) s += (double)bf16_to_f32(Lc[r]) * ak[r];
-    } else {
-      const float* Lc = L + col * ts;
-      for (int64_t r = lane; r < ts; r += 64) s += (double)Lc[r] * ak[r];
-    }
-    s = wave_sum(s);
-    if (lane == 0) rhs[j * ts + col] -= s;
+  double s[8];
+  if (tag[idx]) {
+    const uint16_t* Lh = (const uint16_t*)L;
+    wave_coldot8([=](int64_t r, int64_t c) { return (double)bf16_to_f32(Lh[r + c * ts]); }, ak, col0, false, ts, s);
+  } else {
+    wave_coldot8([=](int64_t r, int64_t c) { return (double)L[r + c * ts]; }, ak, col0, false, ts, s);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rhs[j * ts + col0 + e] -= s[e];
   }
 }
 
@@ -426,14 +422,14 @@ void launch_trsv_fwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, 
                         double* y, hipStream_t s) {
   const int64_t ts = M.ts, NT = M.NT;
   const int T = (int)(ts / BLK);
-  const size_t shm = (size_t)(ts + 256) * sizeof(double);
+  const size_t shm = (size_t)(ts + SOLVE_THREADS) * sizeof(double);
   const int64_t gmax = (nreal + BLK - 1) / BLK;
   for (int64_t k = 0; k < NT; ++k) {
     launch_diag_apply_n(Xd + k * ts * ts, ts, rhs + k * ts, y + k * ts, s);
     const int64_t g0 = (k + 1) * T;
     if (gmax > g0)
-      hipLaunchKernelGGL(k_gemv_fwd_lp, dim3((unsigned)(gmax - g0)), dim3(256), shm, s, M, tag, k, g0, y + k * ts,
-                         rhs);
+      hipLaunchKernelGGL(k_gemv_fwd_lp, dim3((unsigned)(gmax - g0)), dim3(SOLVE_THREADS), shm, s, M, tag, k, g0,
+                         y + k * ts, rhs);
   }
 }
 
@@ -444,7 +440,8 @@ void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, 
   for (int64_t k = NT - 1; k >= 0; --k) {
     launch_diag_apply_t(Xd + k * ts * ts, ts, rhs + k * ts, a + k * ts, s);
     if (k > 0)
-      hipLaunchKernelGGL(k_gemv_bwd_lp, dim3((unsigned)(k * T)), dim3(256), 0, s, M, tag, k, a + k * ts, rhs);
+      hipLaunchKernelGGL(k_gemv_bwd_lp, dim3((unsigned)(k * T)), dim3(SOLVE_THREADS), 0, s, M, tag, k, a + k * ts,
+                         rhs);
   }
 }
 

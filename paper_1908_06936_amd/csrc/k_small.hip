@@ -9,6 +9,7 @@
 
 #include "common.h"
 #include "launch.h"
+#include "solve.h"
 
 namespace exg {
 
@@ -287,81 +288,68 @@ __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64
 
 // ------------------------------------------------------- triangular solves
 // rhs_i -= L_ik y_k for the 128-row blocks g0 <= g < gmax below tile k.
-template <typename OT>
-__global__ __launch_bounds__(256) void k_gemv_fwd(TileMat M, int64_t k, int64_t g0, const double* __restrict__ yk,
-                                                  double* __restrict__ rhs) {
+__global__ __launch_bounds__(SOLVE_THREADS) void k_gemv_fwd(TileMat M, int64_t k, int64_t g0,
+                                                           const double* __restrict__ yk, double* __restrict__ rhs) {
   const int64_t ts = M.ts;
-  extern __shared__ double sy[];  // ts + 256
+  extern __shared__ double sy[];  // ts + SOLVE_THREADS
   double* red = sy + ts;
   const int T = (int)(ts / BLK);
   const int64_t g = g0 + blockIdx.x;
   const int64_t i = g / T;
   const int u = (int)(g % T);
   const int t = threadIdx.x;
-  for (int q = t; q < ts; q += 256) sy[q] = yk[q];
+  for (int q = t; q < ts; q += SOLVE_THREADS) sy[q] = yk[q];
   __syncthreads();
-  const OT* L = (const OT*)M.off + off_index(i, k, M.NT) * ts * ts + u * BLK;
-  const int r = t & 127, h = t >> 7;
-  double s = 0.0;
-  for (int64_t q = h; q < ts; q += 2) s += (double)L[r + q * ts] * sy[q];
-  red[t] = s;
-  __syncthreads();
-  if (h == 0) rhs[i * ts + u * BLK + r] -= red[r] + red[r + 128];
+  const double* L = tptr(M, i, k) + u * BLK;
+  const double s = slab_rowdot([=](int r, int c) { return L[r + (int64_t)c * ts]; }, sy, (int)ts, red);
+  if (t < BLK) rhs[i * ts + u * BLK + t] -= s;
 }
 
 // out = X b on one diagonal tile, X lower triangular (explicit inverse);
 // one 128-row block per workgroup
-__global__ __launch_bounds__(256) void k_diag_apply_n(const double* __restrict__ X, int64_t ts,
-                                                      const double* __restrict__ b, double* __restrict__ out) {
+__global__ __launch_bounds__(SOLVE_THREADS) void k_diag_apply_n(const double* __restrict__ X, int64_t ts,
+                                                               const double* __restrict__ b,
+                                                               double* __restrict__ out) {
   __shared__ double sb[4096];  // ts <= 4096
-  __shared__ double red[256];
+  __shared__ double red[SOLVE_THREADS];
   const int rb = blockIdx.x, t = threadIdx.x;
-  const int64_t cmax = (int64_t)(rb + 1) * BLK;  // X(row, c) = 0 for c >= cmax
-  for (int64_t q = t; q < cmax; q += 256) sb[q] = b[q];
+  const int cmax = (rb + 1) * BLK;  // X(row, c) = 0 for c >= cmax
+  for (int q = t; q < cmax; q += SOLVE_THREADS) sb[q] = b[q];
   __syncthreads();
-  const int r = t & 127, h = t >> 7;
-  const double* Xr = X + rb * BLK + r;
-  double s = 0.0;
-  for (int64_t c = h; c < cmax; c += 2) s += Xr[c * ts] * sb[c];
-  red[t] = s;
-  __syncthreads();
-  if (h == 0) out[rb * BLK + r] = red[r] + red[r + 128];
+  const double* Xr = X + rb * BLK;
+  const double s = slab_rowdot([=](int r, int c) { return Xr[r + (int64_t)c * ts]; }, sb, cmax, red);
+  if (t < BLK) out[rb * BLK + t] = s;
 }
 
 // out = X^T b on one diagonal tile, X lower triangular; one 128-column block
-// per workgroup, one wave per column (lanes run down the column)
-__global__ __launch_bounds__(256) void k_diag_apply_t(const double* __restrict__ X, int64_t ts,
-                                                      const double* __restrict__ b, double* __restrict__ out) {
-  const int cb = blockIdx.x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int n = w; n < BLK; n += 4) {
-    const int64_t col = (int64_t)cb * BLK + n;
-    const double* Xc = X + col * ts;
-    double s = 0.0;
-    for (int64_t r = col + lane; r < ts; r += 64) s += Xc[r] * b[r];
-    s = wave_sum(s);
-    if (lane == 0) out[col] = s;
+// per workgroup, eight columns per wave (lanes run down the columns)
+__global__ __launch_bounds__(SOLVE_THREADS) void k_diag_apply_t(const double* __restrict__ X, int64_t ts,
+                                                               const double* __restrict__ b,
+                                                               double* __restrict__ out) {
+  const int64_t col0 = (int64_t)blockIdx.x * BLK + 8 * (threadIdx.x >> 6);
+  double s[8];
+  wave_coldot8([=](int64_t r, int64_t c) { return X[r + c * ts]; }, b, col0, true, ts, s);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[col0 + e] = s[e];
   }
 }
 
-// rhs_j -= L_kj^T a_k for the 128-column blocks c0 <= c < c1 (columns of tiles j < k).
-template <typename OT>
-__global__ __launch_bounds__(256) void k_gemv_bwd(TileMat M, int64_t k, const double* __restrict__ ak,
-                                                  double* __restrict__ rhs) {
+// rhs_j -= L_kj^T a_k over the 128-column blocks of the tiles j < k (one
+// block per workgroup)
+__global__ __launch_bounds__(SOLVE_THREADS) void k_gemv_bwd(TileMat M, int64_t k, const double* __restrict__ ak,
+                                                           double* __restrict__ rhs) {
   const int64_t ts = M.ts;
   const int T = (int)(ts / BLK);
-  const int64_t cb = blockIdx.x;  // column block over tiles j < k
+  const int64_t cb = blockIdx.x;
   const int64_t j = cb / T;
-  const int v = (int)(cb % T);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const OT* L = (const OT*)M.off + off_index(k, j, M.NT) * ts * ts;
-  for (int n = w; n < BLK; n += 4) {
-    const int64_t col = (int64_t)v * BLK + n;
-    const OT* Lc = L + col * ts;
-    double s = 0.0;
-    for (int64_t r = lane; r < ts; r += 64) s += (double)Lc[r] * ak[r];
-    s = wave_sum(s);
-    if (lane == 0) rhs[j * ts + col] -= s;
+  const int64_t col0 = (cb % T) * BLK + 8 * (threadIdx.x >> 6);
+  const double* L = tptr(M, k, j);
+  double s[8];
+  wave_coldot8([=](int64_t r, int64_t c) { return L[r + c * ts]; }, ak, col0, false, ts, s);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rhs[j * ts + col0 + e] -= s[e];
   }
 }
 
@@ -486,45 +474,35 @@ void launch_potrf_blk(double* A, int64_t lda, double* dinv, double* ldpart, unsi
   hipLaunchKernelGGL(k_potrf_blk, dim3(1), dim3(256), 0, s, A, lda, dinv, ldpart, info, col0);
 }
 
-void launch_trsv_fwd(const TileMat& M, bool off32, const double* Xd, int64_t nreal, double* rhs, double* y,
-                     hipStream_t s) {
+void launch_trsv_fwd(const TileMat& M, const double* Xd, int64_t nreal, double* rhs, double* y, hipStream_t s) {
   const int64_t ts = M.ts, NT = M.NT;
   const int T = (int)(ts / BLK);
-  const size_t shm = (size_t)(ts + 256) * sizeof(double);
+  const size_t shm = (size_t)(ts + SOLVE_THREADS) * sizeof(double);
   const int64_t gmax = (nreal + BLK - 1) / BLK;  // row blocks holding real rows
   for (int64_t k = 0; k < NT; ++k) {
-    hipLaunchKernelGGL(k_diag_apply_n, dim3(T), dim3(256), 0, s, Xd + k * ts * ts, ts, rhs + k * ts, y + k * ts);
+    launch_diag_apply_n(Xd + k * ts * ts, ts, rhs + k * ts, y + k * ts, s);
     const int64_t g0 = (k + 1) * T;
-    if (gmax > g0) {
-      if (off32)
-        hipLaunchKernelGGL(k_gemv_fwd<float>, dim3((unsigned)(gmax - g0)), dim3(256), shm, s, M, k, g0, y + k * ts,
-                           rhs);
-      else
-        hipLaunchKernelGGL(k_gemv_fwd<double>, dim3((unsigned)(gmax - g0)), dim3(256), shm, s, M, k, g0, y + k * ts,
-                           rhs);
-    }
+    if (gmax > g0)
+      hipLaunchKernelGGL(k_gemv_fwd, dim3((unsigned)(gmax - g0)), dim3(SOLVE_THREADS), shm, s, M, k, g0, y + k * ts,
+                         rhs);
   }
 }
 
 void launch_diag_apply_n(const double* Xk, int64_t ts, const double* b, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_diag_apply_n, dim3((unsigned)(ts / BLK)), dim3(256), 0, s, Xk, ts, b, out);
+  hipLaunchKernelGGL(k_diag_apply_n, dim3((unsigned)(ts / BLK)), dim3(SOLVE_THREADS), 0, s, Xk, ts, b, out);
 }
 
 void launch_diag_apply_t(const double* Xk, int64_t ts, const double* b, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_diag_apply_t, dim3((unsigned)(ts / BLK)), dim3(256), 0, s, Xk, ts, b, out);
+  hipLaunchKernelGGL(k_diag_apply_t, dim3((unsigned)(ts / BLK)), dim3(SOLVE_THREADS), 0, s, Xk, ts, b, out);
 }
 
-void launch_trsv_bwd(const TileMat& M, bool off32, const double* Xd, double* rhs, double* a, hipStream_t s) {
+void launch_trsv_bwd(const TileMat& M, const double* Xd, double* rhs, double* a, hipStream_t s) {
   const int64_t ts = M.ts, NT = M.NT;
   const int T = (int)(ts / BLK);
   for (int64_t k = NT - 1; k >= 0; --k) {
-    hipLaunchKernelGGL(k_diag_apply_t, dim3(T), dim3(256), 0, s, Xd + k * ts * ts, ts, rhs + k * ts, a + k * ts);
-    if (k > 0) {
-      if (off32)
-        hipLaunchKernelGGL(k_gemv_bwd<float>, dim3((unsigned)(k * T)), dim3(256), 0, s, M, k, a + k * ts, rhs);
-      else
-        hipLaunchKernelGGL(k_gemv_bwd<double>, dim3((unsigned)(k * T)), dim3(256), 0, s, M, k, a + k * ts, rhs);
-    }
+    launch_diag_apply_t(Xd + k * ts * ts, ts, rhs + k * ts, a + k * ts, s);
+    if (k > 0)
+      hipLaunchKernelGGL(k_gemv_bwd, dim3((unsigned)(k * T)), dim3(SOLVE_THREADS), 0, s, M, k, a + k * ts, rhs);
   }
 }
 

@@ -23,9 +23,8 @@ void launch_sort_locations(const double* x, const double* y, const double* z, in
 void launch_scatter(const double* v, const int32_t* perm, int64_t n, double* out, hipStream_t s);
 void launch_potrf_blk(double* A, int64_t lda, double* dinv, double* ldpart, unsigned long long* info, int64_t col0,
                       hipStream_t s);
-void launch_trsv_fwd(const TileMat& M, bool off32, const double* Xd, int64_t nreal, double* rhs, double* y,
-                     hipStream_t s);
-void launch_trsv_bwd(const TileMat& M, bool off32, const double* Xd, double* rhs, double* a, hipStream_t s);
+void launch_trsv_fwd(const TileMat& M, const double* Xd, int64_t nreal, double* rhs, double* y, hipStream_t s);
+void launch_trsv_bwd(const TileMat& M, const double* Xd, double* rhs, double* a, hipStream_t s);
 void launch_trmv_lower(const TileMat& M, int64_t nreal, const double* e, double* w, hipStream_t s);
 void launch_finalize_loglik(const double* yv, int64_t n, const double* ldpart, int64_t nld, double* out,
                             hipStream_t s);
