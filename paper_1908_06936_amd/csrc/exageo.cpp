@@ -28,7 +28,7 @@ struct Plan {
   bool mixed = false;
   size_t off_diag = 0, off_offt = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
-         off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_p32 = 0, off_tag = 0,
+         off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_p32 = 0, off_pbt = 0, off_tag = 0,
          off_tbox = 0;
   size_t bytes = 0;
 };
@@ -60,6 +60,7 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
     // two halves each: the panel of step k + 1 is built while step k's update reads step k's
     p.off_pbuf = take(2 * (size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8);
     p.off_p32 = take(2 * (size_t)std::max<int64_t>(1, p.NT - 1) * tt * 4);
+    p.off_pbt = take(2 * (size_t)std::max<int64_t>(1, p.NT - 1) * tt * 2);
     p.off_tag = take(noff);
     p.off_tbox = take((size_t)p.NT * 4 * 8);
   }
@@ -287,6 +288,7 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
   // precision the FP64 panel buffer and its FP32 copy alternate between two
   // halves so that panel k + 1 never overwrites the operands of step k.
   hipStream_t S = c->stream, S2 = c->side;
+  const bool any_bf16 = p.mixed && c->timings[11] > 0.0;
   const size_t phalf = (size_t)std::max<int64_t>(1, p.NT - 1) * tt;
   auto panel = [&](int64_t k, hipStream_t s) -> double* {
     double* below = nullptr;
@@ -300,23 +302,26 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
     }
     exg::launch_panel(M.diag + k * tt, below, p.ts, p.NT, k, p.n, at<double>(c, p.off_dinv) + k * p.T * BLKH * BLKH,
                       at<double>(c, p.off_ld) + k * p.T, at<unsigned long long>(c, p.off_info), s);
-    if (p.mixed && k + 1 < p.NT)
+    if (p.mixed && k + 1 < p.NT) {
       exg::launch_panel_scatter(M, k, tag, below, at<float>(c, p.off_p32) + (k & 1) * phalf, s);
+      if (any_bf16) exg::launch_panel_bf16t(M, k, below, at<uint16_t>(c, p.off_pbt) + (k & 1) * phalf, s);
+    }
     return below;
   };
   double* below = panel(0, S);
   for (int64_t k = 0; k + 1 < p.NT; ++k) {
     float* p32 = p.mixed ? at<float>(c, p.off_p32) + (k & 1) * phalf : nullptr;
+    const uint16_t* pbt = p.mixed && any_bf16 ? at<uint16_t>(c, p.off_pbt) + (k & 1) * phalf : nullptr;
     const int slot = EV_UPD0 + 2 * (int)k;
     if (slot + 1 < c->nev_created) rec(c, slot);
     exg::launch_chol_update(M, below, k, p.n, p.mixed, exg::UPD_FIRST_COLUMN, S);
-    if (p.mixed) exg::launch_update_lp(M, tag, p32, k, p.n, exg::UPD_FIRST_COLUMN, S);
+    if (p.mixed) exg::launch_update_lp(M, tag, p32, pbt, k, p.n, exg::UPD_FIRST_COLUMN, S);
     HIPCHK(c, hipEventRecord(c->ev_col, S));
     HIPCHK(c, hipStreamWaitEvent(S2, c->ev_col, 0));
     double* next = panel(k + 1, S2);
     HIPCHK(c, hipEventRecord(c->ev_panel, S2));
     exg::launch_chol_update(M, below, k, p.n, p.mixed, exg::UPD_REST, S);
-    if (p.mixed) exg::launch_update_lp(M, tag, p32, k, p.n, exg::UPD_REST, S);
+    if (p.mixed) exg::launch_update_lp(M, tag, p32, pbt, k, p.n, exg::UPD_REST, S);
     if (slot + 1 < c->nev_created) rec(c, slot + 1);
     HIPCHK(c, hipStreamWaitEvent(S, c->ev_panel, 0));
     below = next;

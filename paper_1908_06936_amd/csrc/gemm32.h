@@ -1,8 +1,10 @@
-// FP32 MFMA block core for the mixed-precision kernels: one 128 x 128 block of
-//   sum_k Aop(m, k) Bop(n, k)
-// accumulated in FP32 on v_mfma_f32_32x32x2f32, with operands read from FP32,
-// FP64 (rounded to nearest FP32) or BF16 (widened exactly) tiles and staged
-// through LDS as FP32.
+// Low-precision MFMA block cores for the mixed-precision kernels: one
+// 128 x 128 block of  sum_k Aop(m, k) Bop(n, k)  accumulated in FP32,
+//   gemm32:    on v_mfma_f32_32x32x2f32, operands read from FP32, FP64
+//              (rounded to nearest FP32) or BF16 (widened exactly) tiles and
+//              staged through LDS as FP32;
+//   gemm_bf16: on v_mfma_f32_16x16x32_bf16, BF16 operands stored with k
+//              contiguous, staged through LDS as they are.
 #pragma once
 
 #include "common.h"
@@ -230,6 +232,89 @@ __device__ __forceinline__ void gemm32_blk(const TA* A, int64_t lda, const TB* B
                                            v16f (&acc)[2][2], float* sm) {
   gemm32<SA, AKC, SB, BKC>([=](int k0) { return A + (AKC ? (int64_t)k0 : (int64_t)k0 * lda); }, lda,
                            [=](int k0) { return B + (BKC ? (int64_t)k0 : (int64_t)k0 * ldb); }, ldb, K, acc, sm);
+}
+
+// ---------------------------------------------------------------- BF16 core
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int GB_BK = 32;                             // k-depth of one stage
+constexpr int GB_LDK = GB_BK + 8;                     // padded LDS row (BF16): 80 bytes
+constexpr int GB_LDS_BYTES = 2 * 2 * BLK * GB_LDK * 2;  // 2 operands x 2 stages
+
+// v_mfma_f32_16x16x32_bf16 (checked on gfx950): operand X lane l holds
+// X[l % 16][8 (l / 16) + e], operand Y lane l holds Y[8 (l / 16) + e][l % 16],
+// e < 8; D = X Y has lane l, register r at D[4 (l / 16) + r][l % 16].
+__device__ __forceinline__ v4f mfma_bf16(v8bf x, v8bf y, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void accb_zero(v4f (&acc)[4][4]) {
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = (v4f){0.f, 0.f, 0.f, 0.f};
+}
+
+// acc += sum_{k < K} Aop(m, k) Bop(n, k) with BF16 operands stored k
+// contiguous: Aop(m, k0 + q) = aptr(k0)[q + m lda] (likewise B); K a multiple
+// of 2 GB_BK, rows 16-byte aligned.  acc[x][y] register r holds output row
+// m = wr*64 + 16 x + (lane & 15) and column n = wc*64 + 16 y + 4 (lane >> 4) + r.
+// Ends with a barrier.
+template <class AP, class BP>
+__device__ __forceinline__ void gemm_bf16(AP aptr, int64_t lda, BP bptr, int64_t ldb, int K, v4f (&acc)[4][4],
+                                          uint16_t* sm) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  uint16_t* sA = sm;
+  uint16_t* sB = sm + 2 * BLK * GB_LDK;
+  u4 ra0[2], rb0[2], ra1[2], rb1[2];
+  auto gload = [&](int k0, u4 (&ra)[2], u4 (&rb)[2]) {
+    const uint16_t* A = aptr(k0);
+    const uint16_t* B = bptr(k0);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int idx = t + 256 * s, m = idx >> 2, k8 = idx & 3;
+      ra[s] = *(const u4*)(A + 8 * k8 + (int64_t)m * lda);
+      rb[s] = *(const u4*)(B + 8 * k8 + (int64_t)m * ldb);
+    }
+  };
+  auto sstore = [&](int buf, const u4 (&ra)[2], const u4 (&rb)[2]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int idx = t + 256 * s, m = idx >> 2, k8 = idx & 3;
+      *(u4*)(sA + buf * BLK * GB_LDK + m * GB_LDK + 8 * k8) = ra[s];
+      *(u4*)(sB + buf * BLK * GB_LDK + m * GB_LDK + 8 * k8) = rb[s];
+    }
+  };
+  auto compute = [&](int cur) {
+    const uint16_t* sa = sA + cur * BLK * GB_LDK + (wr * 64 + (lane & 15)) * GB_LDK + 8 * (lane >> 4);
+    const uint16_t* sb = sB + cur * BLK * GB_LDK + (wc * 64 + (lane & 15)) * GB_LDK + 8 * (lane >> 4);
+    v8bf af[4], bf[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) af[x] = *(const v8bf*)(sa + 16 * x * GB_LDK);
+#pragma unroll
+    for (int y = 0; y < 4; ++y) bf[y] = *(const v8bf*)(sb + 16 * y * GB_LDK);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = mfma_bf16(bf[y], af[x], acc[x][y]);
+  };
+  const int nst = K / GB_BK;  // even
+  gload(0, ra0, rb0);
+  gload(GB_BK, ra1, rb1);
+  sstore(0, ra0, rb0);
+  __syncthreads();
+  for (int s = 0; s < nst; s += 2) {
+    if (s + 2 < nst) gload((s + 2) * GB_BK, ra0, rb0);
+    compute(0);
+    sstore(1, ra1, rb1);
+    __syncthreads();
+    if (s + 3 < nst) gload((s + 3) * GB_BK, ra1, rb1);
+    compute(1);
+    if (s + 2 < nst) sstore(0, ra0, rb0);
+    __syncthreads();
+  }
 }
 
 }  // namespace exg

@@ -140,16 +140,48 @@ __global__ void k_panel_scatter(TileMat M, int64_t k, const uint8_t* __restrict_
     dst[o] = f;
 }
 
-// ------------------------------------------------ FP32 MFMA trailing update
-// C_ij -= L_ik L_jk^T for the off-diagonal targets k < j < i < NT, with the
-// operands taken from the FP32 rounding of the FP64 panel (p32 tile q holds
-// L_{k+1+q, k}), so that a BF16-stored panel tile never feeds its rounding
-// error into targets near the diagonal.  One 256-thread block computes one
-// 128 x 128 block of a target tile.
+// pbt tile q = pbuf tile q rounded to BF16 (nearest even, through FP32) and
+// transposed, so that the BF16 update reads its operands k contiguous:
+// element (m, kk) of tile q at pbt[q ts^2 + m ts + kk].  One 64 x 64 block
+// per workgroup, transposed through LDS.
+__global__ __launch_bounds__(256) void k_panel_bf16t(const double* __restrict__ pbuf, uint16_t* __restrict__ pbt,
+                                                     int64_t ts, int64_t count) {
+  __shared__ uint16_t sb[64][66];
+  const int64_t nb = ts / 64;
+  const int64_t b = blockIdx.x;
+  if (b >= count * nb * nb) return;
+  const int64_t q = b / (nb * nb), r = b % (nb * nb);
+  const int64_t m0 = (r % nb) * 64, k0 = (r / nb) * 64;
+  const double* src = pbuf + q * ts * ts;
+  uint16_t* dst = pbt + q * ts * ts;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int m = t & 63, kk = (t >> 6) + 4 * p;
+    sb[kk][m] = f32_to_bf16((float)src[(m0 + m) + (k0 + kk) * ts]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int kk = t & 63, m = (t >> 6) + 4 * p;
+    dst[(m0 + m) * ts + k0 + kk] = sb[kk][m];
+  }
+}
+
+// ------------------------------------------- low-precision trailing update
+// C_ij -= L_ik L_jk^T for the off-diagonal targets k < j < i < NT.  FP32
+// targets run on FP32 MFMA with operands rounded to FP32 from the FP64 panel
+// (p32 tile q holds L_{k+1+q, k}), so that a BF16-stored panel tile never
+// feeds its rounding error into targets near the diagonal; BF16 targets run
+// on BF16 MFMA with FP32 accumulation from the BF16 transposed panel copy pbt
+// (null when the step has no BF16 targets).  One 256-thread block computes
+// one 128 x 128 block of a target tile.
 __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* __restrict__ tag,
-                                                      const float* __restrict__ p32, int T, int64_t k,
+                                                      const float* __restrict__ p32,
+                                                      const uint16_t* __restrict__ pbt, int T, int64_t k,
                                                       int64_t nreal, int64_t nb, int mode, int64_t off) {
-  __shared__ float sm[G32_LDS];
+  constexpr int SMB = G32_LDS * 4 > GB_LDS_BYTES ? G32_LDS * 4 : GB_LDS_BYTES;
+  __shared__ __attribute__((aligned(16))) char smraw[SMB];
   const int64_t ts = M.ts, tt = ts * ts;
   const int64_t b = blockIdx.x;
   if (b >= nb) return;
@@ -160,12 +192,36 @@ __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* 
   pair_map(mode, off, p, &a, &c);  // c <= a
   const int64_t i = k + 2 + a, j = k + 1 + c;
   if (i * ts + u * BLK >= nreal) return;  // padded rows: update is zero
-  v16f acc[2][2];
-  acc32_zero(acc);
-  gemm32_blk<SRC_F32, false, SRC_F32, false>(p32 + (a + 1) * tt + u * BLK, ts, p32 + c * tt + v * BLK, ts, (int)ts,
-                                              acc, sm);
   const int64_t ic = off_index(i, j, M.NT);
-  acc32_update((float*)M.off + ic * tt, tag[ic] != 0, u * BLK + (int64_t)v * BLK * ts, ts, acc, -1.f);
+  float* C = (float*)M.off + ic * tt;
+  if (tag[ic] && pbt) {
+    v4f acc[4][4];
+    accb_zero(acc);
+    const uint16_t* A = pbt + (a + 1) * tt + (int64_t)u * BLK * ts;
+    const uint16_t* B = pbt + c * tt + (int64_t)v * BLK * ts;
+    gemm_bf16([=](int k0) { return A + k0; }, ts, [=](int k0) { return B + k0; }, ts, (int)ts, acc,
+              (uint16_t*)smraw);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+    uint16_t* Ch = (uint16_t*)C + u * BLK + (int64_t)v * BLK * ts;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int m = wr * 64 + 16 * x + (lane & 15);
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int n = wc * 64 + 16 * y + 4 * (lane >> 4) + r;
+          const int64_t o = m + (int64_t)n * ts;
+          Ch[o] = f32_to_bf16(bf16_to_f32(Ch[o]) - acc[x][y][r]);
+        }
+    }
+  } else {
+    v16f acc[2][2];
+    acc32_zero(acc);
+    gemm32_blk<SRC_F32, false, SRC_F32, false>(p32 + (a + 1) * tt + u * BLK, ts, p32 + c * tt + v * BLK, ts, (int)ts,
+                                                acc, (float*)smraw);
+    acc32_update(C, tag[ic] != 0, u * BLK + (int64_t)v * BLK * ts, ts, acc, -1.f);
+  }
 }
 
 // ------------------------------------------------- solves on mixed tiles
@@ -401,8 +457,15 @@ void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const
                      count);
 }
 
-void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, int64_t k, int64_t nreal, int part,
-                      hipStream_t s) {
+void launch_panel_bf16t(const TileMat& M, int64_t k, const double* pbuf, uint16_t* pbt, hipStream_t s) {
+  const int64_t count = M.NT - k - 1;
+  if (count <= 0) return;
+  const int64_t nb = M.ts / 64;
+  hipLaunchKernelGGL(k_panel_bf16t, dim3((unsigned)(count * nb * nb)), dim3(256), 0, s, pbuf, pbt, M.ts, count);
+}
+
+void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, const uint16_t* pbt, int64_t k,
+                      int64_t nreal, int part, hipStream_t s) {
   const int T = (int)(M.ts / BLK);
   const int64_t m = M.NT - k - 2;  // strictly-lower pairs among the m + 1 trailing tiles
   if (m <= 0) return;
@@ -415,7 +478,8 @@ void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, in
   }
   if (npairs <= 0) return;
   const int64_t nblk = npairs * T * T;
-  hipLaunchKernelGGL(k_update_lp, dim3((unsigned)nblk), dim3(256), 0, s, M, tag, p32, T, k, nreal, nblk, mode, off);
+  hipLaunchKernelGGL(k_update_lp, dim3((unsigned)nblk), dim3(256), 0, s, M, tag, p32, pbt, T, k, nreal, nblk, mode,
+                     off);
 }
 
 void launch_trsv_fwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, int64_t nreal, double* rhs,

@@ -44,8 +44,10 @@ void launch_tile_bbox(const double* xs, const double* ys, int64_t ts, int64_t NT
 void launch_panel_gather(const TileMat& M, int64_t k, const uint8_t* tag, double* pbuf, hipStream_t s);
 void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const double* pbuf, float* p32,
                           hipStream_t s);
-void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, int64_t k, int64_t nreal, int part,
-                      hipStream_t s);
+// BF16 copy of the FP64 panel of step k, each tile transposed (k contiguous)
+void launch_panel_bf16t(const TileMat& M, int64_t k, const double* pbuf, uint16_t* pbt, hipStream_t s);
+void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, const uint16_t* pbt, int64_t k,
+                      int64_t nreal, int part, hipStream_t s);
 void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, double* rhs, double* a,
                         hipStream_t s);
 // one step of the mixed inverse (FP32 off-diagonal tiles of L^-1, FP32 buffer P)
