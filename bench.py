@@ -65,6 +65,114 @@ def cpu_baseline(n_full: int, theta, sample_n: int) -> dict:
                       f"scaled by (n/{sample_n})^3 to n={n_full}"}
 
 
+def mle_study(args) -> int:
+    """Wall clock of the estimators (one JSON line).
+
+    * n = 400 (20 x 20 jittered grid, theta = (1, 0.1, 0.5)): one l and the
+      derivative-free MLE from the lower bound, as in the paper's example.
+    * n = 40,000 (200 x 200 jittered grid, true theta = (1, 0.1, 0.5) and
+      (1, 0.1, 0.8), start (0.5, 0.3, 0.5)): FP64 derivative-free vs FP64 and
+      mixed-precision L-BFGS-B, wall clock, theta-hat and l(theta-hat)
+      re-evaluated in FP64.
+    * n = side^2 (default 160,000): one FP64 l, one FP64 (l, grad l) and one
+      mixed (l, grad l) at the true theta (the full estimators at this size
+      take hours of derivative-free evaluations).
+    """
+    import torch
+
+    import inputgen
+    import paper_1908_06936_amd as exa
+
+    dev = torch.device("cuda:0")
+    out = {"study": "mle", "data": "synthetic"}
+
+    def field(m, th, seed, ts):
+        x, y = inputgen.jittered_grid(m, seed=seed)
+        e = inputgen.normals(x.size, seed=seed)
+        X, Y, E = (torch.as_tensor(a, device=dev) for a in (x, y, e))
+        ctx = exa.Context(ts=ts)
+        Z = ctx.simulate(X, Y, th, E)
+        torch.cuda.synchronize()
+        return ctx, X, Y, Z
+
+    # n = 400, one tile
+    th1 = [1.0, 0.1, 0.5]
+    ctx, X, Y, Z = field(20, th1, 0, 512)
+    ctx.loglik(X, Y, Z, th1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    l1 = ctx.loglik(X, Y, Z, th1)
+    t1 = time.perf_counter()
+    lb, ub = [0.001, 0.001, 0.001], [5.0, 5.0, 5.0]
+    th_hat, l_hat, st = ctx.mle(X, Y, Z, lb, ub, tol=1e-4, method="dfo")
+    out["n400"] = {"loglik_at_true": l1, "loglik_ms": 1e3 * (t1 - t0), "dfo_theta_hat": th_hat, "dfo_loglik": l_hat,
+                   "dfo_stats": st}
+    print(f"[mle] n=400 done: {st}", file=sys.stderr, flush=True)
+    ctx.close()
+    del ctx
+
+    # n = 40,000: estimators compared, for a rough (nu = 0.5) and a smoother
+    # (nu = 0.8) field; evaluation caps keep each run within a few minutes
+    lb, ub, th0 = [0.01, 0.01, 0.1], [5.0, 2.0, 3.0], [0.5, 0.3, 0.5]
+    out["n40000_grid"] = {}
+    for th_true in ([1.0, 0.1, 0.5], [1.0, 0.1, 0.8]):
+        ctx, X, Y, Z = field(200, th_true, 1, 768)
+        runs = {}
+        for label, meth, prec, cap in (("fp64_dfo", "dfo", "fp64", 400), ("fp64_lbfgsb", "lbfgsb", "fp64", 80),
+                                       ("mixed_lbfgsb", "lbfgsb", "mixed", 80)):
+            t0 = time.perf_counter()
+            try:
+                th_hat, l_hat, st = ctx.mle(X, Y, Z, lb, ub, theta0=th0, tol=1e-4, max_iters=cap, method=meth,
+                                            precision=prec)
+            except exa.ExaGeoError as err:
+                runs[label] = {"error": str(err)}
+                continue
+            wall = time.perf_counter() - t0
+            l64 = ctx.loglik_status(X, Y, Z, th_hat, "fp64")[1]
+            runs[label] = {"theta_hat": th_hat, "loglik_reported": l_hat, "loglik_fp64_at_theta_hat": l64,
+                           "wall_s": wall, "max_evals": cap, "stats": st}
+            print(f"[mle] n=40000 nu={th_true[2]} {label}: {wall:.1f} s, theta {th_hat}, {st}", file=sys.stderr,
+                  flush=True)
+        ref = runs.get("fp64_dfo", {}).get("loglik_fp64_at_theta_hat")
+        for label, d in runs.items():
+            if ref is not None and "loglik_fp64_at_theta_hat" in d:
+                d["rel_dl_vs_fp64_dfo"] = abs(d["loglik_fp64_at_theta_hat"] - ref) / abs(ref)
+                d["speedup_vs_fp64_dfo"] = runs["fp64_dfo"]["wall_s"] / d["wall_s"]
+        out["n40000_grid"][f"nu={th_true[2]}"] = {"theta_true": th_true, "theta0": th0, "lb": lb, "ub": ub,
+                                                  "runs": runs}
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    th_true = [1.0, 0.1, 0.8]
+
+    # large n: single evaluations
+    m = args.big_n_side
+    ctx, X, Y, Z = field(m, th_true, 2, 768)
+    big = {"n": m * m}
+    for label, prec, grad in (("fp64_loglik", "fp64", False), ("fp64_loglik_grad", "fp64", True),
+                              ("mixed_loglik_grad", "mixed", True)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if grad:
+            st_, v, info = ctx.loglik_status(X, Y, Z, th_true, prec)
+            if st_ == 0:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                v, g = ctx.loglik_grad(X, Y, Z, th_true, prec)
+            else:
+                g = None
+        else:
+            st_, v, info = ctx.loglik_status(X, Y, Z, th_true, prec)
+            g = None
+        torch.cuda.synchronize()
+        big[label] = {"status": exa.STATUS_NAMES.get(st_, st_), "s": time.perf_counter() - t0, "loglik": v, "grad": g}
+        print(f"[mle] n={m * m} {label}: {big[label]['s']:.1f} s status {big[label]['status']}", file=sys.stderr,
+              flush=True)
+    out["large"] = big
+    print(json.dumps(out))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +184,10 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=1500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--mle-study", action="store_true",
+                    help="instead of the throughput step: the MLE comparisons (FP64 derivative-free vs "
+                         "gradient-based and mixed precision) and single evaluations at n = 160,000")
+    ap.add_argument("--big-n-side", type=int, default=400, help="grid side of the large single evaluations")
     args = ap.parse_args()
 
     if args.copy_calibration:
@@ -88,6 +200,9 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8}))
         return 0
+
+    if args.mle_study:
+        return mle_study(args)
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "

@@ -102,6 +102,15 @@ exageo_status exageo_set_workspace(exageo_ctx *ctx, void *dev_ptr, size_t bytes)
  * 0 disables BF16 (FP32 off-diagonal only).  Default 3.0.  EINVAL if < 0. */
 exageo_status exageo_set_mixed_policy(exageo_ctx *ctx, double band_factor);
 
+/* FP64 band of the mixed-precision policy (the double-precision tiles near
+ * the diagonal of the paper's mixed-precision structure, Section 2.1 and
+ * Fig. 1(d)): an off-diagonal tile whose two location blocks have bounding
+ * boxes closer than fp64_band_factor * beta is stored and updated in FP64,
+ * closest first, up to 4 NT such tiles (the rest stay FP32).  The BF16 band
+ * takes precedence.  0 (default) keeps every off-diagonal tile in FP32 or
+ * BF16.  EINVAL if < 0. */
+exageo_status exageo_set_mixed_fp64_band(exageo_ctx *ctx, double fp64_band_factor);
+
 /* Text of the last error of this context ("" if none).  Valid until the next
  * call on the context. */
 const char *exageo_last_error(const exageo_ctx *ctx);
@@ -155,7 +164,8 @@ exageo_status exageo_mle(exageo_ctx *ctx, int64_t n, const double *x, const doub
  *   6 solve+reduce ms, 7 gradient ms, 8 Cholesky flops (n^3/3 + n^2/2 + n/6,
  *   FP64 equivalent), 9 number of FP64 trailing-update (k_chol_update)
  *   launches, 10 precision used, 11 fraction of off-diagonal tiles in BF16,
- *   12 fraction in FP32, 13 number of factorisation steps with an update.
+ *   12 fraction in FP32, 13 number of factorisation steps with an update,
+ *   14 fraction of off-diagonal tiles in the FP64 band.
  * Returns the number of values written. */
 int exageo_get_timings(const exageo_ctx *ctx, double *out, int nmax);
 exageo_status exageo_set_profiling(exageo_ctx *ctx, int on);

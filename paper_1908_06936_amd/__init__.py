@@ -70,7 +70,7 @@ class Context:
     """
 
     def __init__(self, ts: int = 768, device: int | None = None, stream: torch.cuda.Stream | None = None,
-                 band_factor: float = 3.0):
+                 band_factor: float = 3.0, fp64_band: float = 0.0):
         self._lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible to torch")
@@ -84,7 +84,7 @@ class Context:
         self._h = h
         self._ws = None
         self._ws_key = None
-        self.set_mixed_policy(band_factor)
+        self.set_mixed_policy(band_factor, fp64_band)
 
     # ------------------------------------------------------------ plumbing
     def _stream_handle(self):
@@ -102,6 +102,7 @@ class Context:
             self._lib.exageo_set_workspace(self._h, None, 0)
             self._ws = None
             torch.cuda.synchronize(self.device)
+            torch.cuda.empty_cache()  # return the old block before taking a larger one
             self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
             st = self._lib.exageo_set_workspace(self._h, ctypes.c_void_p(self._ws.data_ptr()), need)
             self._check(st, "set_workspace")
@@ -126,8 +127,12 @@ class Context:
         except Exception:
             pass
 
-    def set_mixed_policy(self, band_factor: float):
+    def set_mixed_policy(self, band_factor: float, fp64_band: float | None = None):
+        """Mixed precision: BF16 for tiles at least band_factor * beta apart,
+        FP64 for tiles closer than fp64_band * beta (unchanged if None)."""
         self._check(self._lib.exageo_set_mixed_policy(self._h, float(band_factor)), "set_mixed_policy")
+        if fp64_band is not None:
+            self._check(self._lib.exageo_set_mixed_fp64_band(self._h, float(fp64_band)), "set_mixed_fp64_band")
 
     def set_profiling(self, on: bool = True):
         self._check(self._lib.exageo_set_profiling(self._h, int(on)), "set_profiling")
@@ -136,7 +141,8 @@ class Context:
         buf = (ctypes.c_double * 16)()
         m = self._lib.exageo_get_timings(self._h, buf, 16)
         keys = ["total_ms", "prep_ms", "gen_ms", "chol_ms", "update_kernel_ms", "update_flops", "solve_ms",
-                "grad_ms", "chol_flops", "update_launches", "precision", "frac_bf16", "frac_fp32", "update_steps"]
+                "grad_ms", "chol_flops", "update_launches", "precision", "frac_bf16", "frac_fp32", "update_steps",
+                "frac_fp64"]
         return {k: buf[i] for i, k in enumerate(keys[:m])}
 
     # ---------------------------------------------------------- operations

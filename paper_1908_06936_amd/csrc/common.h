@@ -61,7 +61,19 @@ struct TileMat {
   double* diag;
   void* off;
   int64_t ts, NT;
+  // mixed precision only: FP64 band tiles live in a pool of FP64 tiles;
+  // pidx[off_index(i, j)] is the pool slot of tile (i, j) (-1: not a band tile)
+  double* pool = nullptr;
+  const int32_t* pidx = nullptr;
 };
+
+// precision tag of an off-diagonal tile in mixed precision
+enum TileTag { TAG_F32 = 0, TAG_BF16 = 1, TAG_F64 = 2 };
+
+// FP64 band tile with off-diagonal index idx (mixed precision)
+__device__ __forceinline__ double* band64(const TileMat& M, int64_t idx) {
+  return M.pool + (int64_t)M.pidx[idx] * M.ts * M.ts;
+}
 
 __host__ __device__ __forceinline__ int64_t off_index(int64_t i, int64_t j, int64_t NT) {
   return j * (NT - 1) - j * (j - 1) / 2 + (i - j - 1);
@@ -86,7 +98,7 @@ __device__ __forceinline__ void tri_decode(int64_t p, int64_t* a, int64_t* b) {
 // tile; the first trailing column (c = 0) is updated apart from the rest so
 // that the next panel can be factored while the rest of the update runs.
 enum UpdatePart { UPD_ALL = 0, UPD_FIRST_COLUMN = 1, UPD_REST = 2 };
-enum PairMap { PAIRS_TRI = 0, PAIRS_DIAG = 1, PAIRS_COL = 2 };
+enum PairMap { PAIRS_TRI = 0, PAIRS_DIAG = 1, PAIRS_COL = 2, PAIRS_LIST = 3 };
 
 // pair group p -> (a, c): PAIRS_TRI the p-th lower pair shifted by off on
 // both sides, PAIRS_DIAG a = c = p + off, PAIRS_COL a = p + off and c = 0

@@ -21,6 +21,7 @@ namespace {
 constexpr int64_t BLKH = 128;
 constexpr int QNB = 10, QNK = 192, QW = 5;  // quadrature table (matern_dev.h)
 constexpr int NEV = 512;                     // profiling events
+constexpr int64_t kBandPoolPerColumn = 4;    // FP64 band pool size, tiles per tile column
 
 struct Plan {
   int64_t n = 0, ts = 0, NT = 0, T = 0, npad = 0, P = 0;
@@ -29,7 +30,8 @@ struct Plan {
   size_t off_diag = 0, off_offt = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
          off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_p32 = 0, off_pbt = 0, off_tag = 0,
-         off_tbox = 0;
+         off_tbox = 0, off_pool = 0, off_pidx = 0, off_bli = 0, off_blj = 0;
+  int64_t pool_cap = 0;  // mixed precision: FP64 band tiles the pool can hold
   size_t bytes = 0;
 };
 
@@ -63,6 +65,12 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
     p.off_pbt = take(2 * (size_t)std::max<int64_t>(1, p.NT - 1) * tt * 2);
     p.off_tag = take(noff);
     p.off_tbox = take((size_t)p.NT * 4 * 8);
+    // FP64 band: at most kBandPoolPerColumn tiles per tile column on average
+    p.pool_cap = std::min<int64_t>((int64_t)noff, kBandPoolPerColumn * p.NT);
+    p.off_pool = take((size_t)std::max<int64_t>(1, p.pool_cap) * tt * 8);
+    p.off_pidx = take(noff * 4);
+    p.off_bli = take((size_t)std::max<int64_t>(1, p.pool_cap) * 4);
+    p.off_blj = take((size_t)std::max<int64_t>(1, p.pool_cap) * 4);
   }
   p.off_xd = take((size_t)p.NT * tt * 8);
   // FP64 inverse: FP64 staging buffer (the mixed inverse stages in the FP32 panel copy)
@@ -95,7 +103,8 @@ struct exageo_ctx {
   int device = 0;
   int64_t ts = 768;
   hipStream_t stream = nullptr;
-  double band_factor = 3.0;
+  double band_factor = 3.0;     // BF16 at or beyond band_factor * beta
+  double fp64_band_factor = 0.0;  // FP64 below fp64_band_factor * beta
   bool profiling = false;
   std::string err;
   // workspace
@@ -111,6 +120,11 @@ struct exageo_ctx {
   std::vector<double> tbox;
   uint8_t* htag = nullptr;
   size_t htag_bytes = 0;
+  // FP64 band: pool slot per off-diagonal tile, band list (column-major
+  // order) and the first list entry of each tile column, all host copies
+  int32_t* hband = nullptr;  // pinned: pidx (noff) then li, lj (pool_cap each)
+  size_t hband_words = 0;
+  std::vector<int64_t> bfirst;
   // side stream (default priority) for the lookahead panel, and its events
   hipStream_t side = nullptr;
   hipEvent_t ev_col = nullptr, ev_panel = nullptr;
@@ -216,16 +230,28 @@ exageo_status prepare_locations(exageo_ctx* c, const Plan& p, const double* x, c
 // Precision of every off-diagonal tile (0 = FP32, 1 = BF16): BF16 when the
 // minimum distance between the bounding boxes of the two location blocks is
 // at least band_factor * beta.  Returns the BF16 fraction.
-exageo_status upload_tags(exageo_ctx* c, const Plan& p, double beta, double* frac_bf16) {
+exageo_status upload_tags(exageo_ctx* c, const Plan& p, double beta, double* frac_bf16, double* frac_fp64) {
   const size_t noff = (size_t)std::max<int64_t>(1, p.NT * (p.NT - 1) / 2);
+  const size_t words = noff + 2 * (size_t)std::max<int64_t>(1, p.pool_cap);
   if (c->htag_bytes < noff) {
     if (c->htag) HIPCHK(c, hipHostFree(c->htag));
     c->htag = nullptr;
     HIPCHK(c, hipHostMalloc((void**)&c->htag, noff));
     c->htag_bytes = noff;
   }
+  if (c->hband_words < words) {
+    if (c->hband) HIPCHK(c, hipHostFree(c->hband));
+    c->hband = nullptr;
+    HIPCHK(c, hipHostMalloc((void**)&c->hband, words * 4));
+    c->hband_words = words;
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));  // previous upload consumed
-  const double band = c->band_factor * beta;
+  const double band16 = c->band_factor * beta, band64 = c->fp64_band_factor * beta;
+  int32_t* pidx = c->hband;
+  int32_t* li = c->hband + noff;
+  int32_t* lj = li + std::max<int64_t>(1, p.pool_cap);
+  // candidates for the FP64 band: closest first, at most pool_cap of them
+  std::vector<std::pair<double, int64_t>> cand;  // (distance, off index)
   int64_t nbf = 0, ntot = 0;
   for (int64_t j = 0; j < p.NT; ++j) {
     const double* bj = &c->tbox[4 * j];
@@ -233,15 +259,53 @@ exageo_status upload_tags(exageo_ctx* c, const Plan& p, double beta, double* fra
       const double* bi = &c->tbox[4 * i];
       const double dx = std::max(0.0, std::max(bi[0] - bj[1], bj[0] - bi[1]));
       const double dy = std::max(0.0, std::max(bi[2] - bj[3], bj[2] - bi[3]));
-      const bool bf = c->band_factor > 0.0 && std::sqrt(dx * dx + dy * dy) >= band;
-      c->htag[exg::off_index(i, j, p.NT)] = bf ? 1 : 0;
-      nbf += bf;
+      const double d = std::sqrt(dx * dx + dy * dy);
+      const int64_t idx = exg::off_index(i, j, p.NT);
+      pidx[idx] = -1;
+      const bool bf = c->band_factor > 0.0 && d >= band16;
+      c->htag[idx] = bf ? exg::TAG_BF16 : exg::TAG_F32;
+      if (!bf && d < band64) cand.emplace_back(d, idx);
       ++ntot;
     }
   }
-  if (p.NT == 1) c->htag[0] = 0;
+  if ((int64_t)cand.size() > p.pool_cap) {
+    std::stable_sort(cand.begin(), cand.end(),
+                     [](const std::pair<double, int64_t>& u, const std::pair<double, int64_t>& v) {
+                       return u.first < v.first;
+                     });
+    cand.resize((size_t)p.pool_cap);
+  }
+  for (const auto& e : cand) c->htag[e.second] = exg::TAG_F64;
+  // band list in column-major tile order; pool slots follow the list
+  c->bfirst.assign((size_t)p.NT + 1, 0);
+  int64_t nb64 = 0;
+  for (int64_t j = 0; j < p.NT; ++j) {
+    c->bfirst[j] = nb64;
+    for (int64_t i = j + 1; i < p.NT; ++i) {
+      const int64_t idx = exg::off_index(i, j, p.NT);
+      if (c->htag[idx] == exg::TAG_F64) {
+        pidx[idx] = (int32_t)nb64;
+        li[nb64] = (int32_t)i;
+        lj[nb64] = (int32_t)j;
+        ++nb64;
+      } else if (c->htag[idx] == exg::TAG_BF16) {
+        ++nbf;
+      }
+    }
+  }
+  c->bfirst[p.NT] = nb64;
+  if (p.NT == 1) {
+    c->htag[0] = exg::TAG_F32;
+    pidx[0] = -1;
+  }
   HIPCHK(c, hipMemcpyAsync(at<uint8_t>(c, p.off_tag), c->htag, noff, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_pidx), pidx, noff * 4, hipMemcpyHostToDevice, c->stream));
+  if (nb64 > 0) {
+    HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_bli), li, (size_t)nb64 * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_blj), lj, (size_t)nb64 * 4, hipMemcpyHostToDevice, c->stream));
+  }
   *frac_bf16 = ntot ? (double)nbf / (double)ntot : 0.0;
+  *frac_fp64 = ntot ? (double)nb64 / (double)ntot : 0.0;
   return EXAGEO_OK;
 }
 
@@ -251,6 +315,10 @@ exg::TileMat tilemat(exageo_ctx* c, const Plan& p) {
   M.off = at<void>(c, p.off_offt);
   M.ts = p.ts;
   M.NT = p.NT;
+  if (p.mixed) {
+    M.pool = at<double>(c, p.off_pool);
+    M.pidx = at<int32_t>(c, p.off_pidx);
+  }
   return M;
 }
 
@@ -267,13 +335,15 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
   c->timings[10] = p.mixed ? EXAGEO_MIXED : EXAGEO_FP64;
   c->timings[11] = 0.0;
   c->timings[12] = 0.0;
+  c->timings[14] = 0.0;
   if (p.mixed) {
-    double fbf = 0.0;
-    exageo_status st = upload_tags(c, p, theta[1], &fbf);
+    double fbf = 0.0, f64 = 0.0;
+    exageo_status st = upload_tags(c, p, theta[1], &fbf, &f64);
     if (st) return st;
     tag = at<uint8_t>(c, p.off_tag);
     c->timings[11] = fbf;
-    c->timings[12] = p.NT > 1 ? 1.0 - fbf : 0.0;
+    c->timings[12] = p.NT > 1 ? 1.0 - fbf - f64 : 0.0;
+    c->timings[14] = f64;
   }
   exg::launch_quad_table(theta, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   exg::launch_fill_info(at<unsigned long long>(c, p.off_info), c->stream);
@@ -289,6 +359,8 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
   // halves so that panel k + 1 never overwrites the operands of step k.
   hipStream_t S = c->stream, S2 = c->side;
   const bool any_bf16 = p.mixed && c->timings[11] > 0.0;
+  const int32_t* bli = p.mixed ? at<int32_t>(c, p.off_bli) : nullptr;
+  const int32_t* blj = p.mixed ? at<int32_t>(c, p.off_blj) : nullptr;
   const size_t phalf = (size_t)std::max<int64_t>(1, p.NT - 1) * tt;
   auto panel = [&](int64_t k, hipStream_t s) -> double* {
     double* below = nullptr;
@@ -315,13 +387,21 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
     const int slot = EV_UPD0 + 2 * (int)k;
     if (slot + 1 < c->nev_created) rec(c, slot);
     exg::launch_chol_update(M, below, k, p.n, p.mixed, exg::UPD_FIRST_COLUMN, S);
-    if (p.mixed) exg::launch_update_lp(M, tag, p32, pbt, k, p.n, exg::UPD_FIRST_COLUMN, S);
+    if (p.mixed) {
+      const int64_t e0 = c->bfirst[k + 1], e1 = c->bfirst[k + 2];
+      exg::launch_band_update(M, below, k, p.n, bli, blj, e0, e1 - e0, S);
+      exg::launch_update_lp(M, tag, p32, pbt, k, p.n, exg::UPD_FIRST_COLUMN, S);
+    }
     HIPCHK(c, hipEventRecord(c->ev_col, S));
     HIPCHK(c, hipStreamWaitEvent(S2, c->ev_col, 0));
     double* next = panel(k + 1, S2);
     HIPCHK(c, hipEventRecord(c->ev_panel, S2));
     exg::launch_chol_update(M, below, k, p.n, p.mixed, exg::UPD_REST, S);
-    if (p.mixed) exg::launch_update_lp(M, tag, p32, pbt, k, p.n, exg::UPD_REST, S);
+    if (p.mixed) {
+      const int64_t e0 = c->bfirst[k + 2], e1 = c->bfirst[p.NT];
+      exg::launch_band_update(M, below, k, p.n, bli, blj, e0, e1 - e0, S);
+      exg::launch_update_lp(M, tag, p32, pbt, k, p.n, exg::UPD_REST, S);
+    }
     if (slot + 1 < c->nev_created) rec(c, slot + 1);
     HIPCHK(c, hipStreamWaitEvent(S, c->ev_panel, 0));
     below = next;
@@ -472,6 +552,7 @@ void exageo_destroy(exageo_ctx* c) {
   if (c->ws && c->ws_owned) (void)hipFree(c->ws);
   if (c->hres) (void)hipHostFree(c->hres);
   if (c->htag) (void)hipHostFree(c->htag);
+  if (c->hband) (void)hipHostFree(c->hband);
   for (int i = 0; i < c->nev_created; ++i) (void)hipEventDestroy(c->ev[i]);
   if (c->side) {
     (void)hipStreamSynchronize(c->side);
@@ -503,6 +584,12 @@ exageo_status exageo_set_workspace(exageo_ctx* c, void* dev_ptr, size_t bytes) {
   c->ws = (char*)dev_ptr;
   c->ws_bytes = dev_ptr ? bytes : 0;
   c->ws_owned = false;
+  return EXAGEO_OK;
+}
+
+exageo_status exageo_set_mixed_fp64_band(exageo_ctx* c, double fp64_band_factor) {
+  if (!c || !(fp64_band_factor >= 0.0) || !std::isfinite(fp64_band_factor)) return EXAGEO_EINVAL;
+  c->fp64_band_factor = fp64_band_factor;
   return EXAGEO_OK;
 }
 

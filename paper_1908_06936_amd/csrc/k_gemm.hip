@@ -27,10 +27,13 @@ namespace exg {
 // -------------------------------------------------------------- Cholesky
 // trailing update of step k over the tiles (i, j), k < j <= i < NT
 // below: the FP64 tiles (k+1, k), ..., (NT-1, k) of column k, contiguous.
-// diag_only: update only the diagonal tiles (j, j) (mixed precision, where the
-// off-diagonal targets are updated by the lower-precision kernels).
+// Mixed precision runs it only on its FP64 targets: the diagonal tiles
+// (PAIRS_DIAG) and the FP64 band tiles, given as a list of (i, j) entries
+// off, off + 1, ... (PAIRS_LIST; stored in the band pool).
 __global__ __launch_bounds__(256, 2) void k_chol_update(TileMat M, const double* __restrict__ below, int T, int64_t k,
-                                                        int64_t nreal, int64_t nb, int mode, int64_t off) {
+                                                        int64_t nreal, int64_t nb, int mode, int64_t off,
+                                                        const int32_t* __restrict__ li,
+                                                        const int32_t* __restrict__ lj) {
   __shared__ double sm[GEMM_LDS];
   const int64_t ts = M.ts;
   const int64_t b = blockIdx.x;
@@ -39,13 +42,19 @@ __global__ __launch_bounds__(256, 2) void k_chol_update(TileMat M, const double*
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
   int64_t a, c;
-  pair_map(mode, off, p, &a, &c);
+  if (mode == PAIRS_LIST) {
+    a = li[off + p] - k - 1;
+    c = lj[off + p] - k - 1;
+  } else {
+    pair_map(mode, off, p, &a, &c);
+  }
   const int64_t i = k + 1 + a, j = k + 1 + c;
   if (i == j && u < v) return;
   if (i * ts + u * BLK >= nreal || j * ts + v * BLK >= nreal) return;  // padding: update is zero
   const double* A = below + a * ts * ts + u * BLK;
   const double* B = below + c * ts * ts + v * BLK;
-  double* C = tptr(M, i, j) + u * BLK + (int64_t)v * BLK * ts;
+  double* C = ((i == j || !M.pool) ? tptr(M, i, j) : band64(M, off_index(i, j, M.NT))) + u * BLK +
+              (int64_t)v * BLK * ts;
   v4d acc[4][4];
   acc_zero(acc);
   gemm_blk<false, false>(A, ts, B, ts, (int)ts, acc, sm);
@@ -279,7 +288,17 @@ void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_
   }
   if (npairs <= 0) return;
   const int64_t nblk = npairs * T * T;
-  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, M, below, T, k, nreal, nblk, mode, off);
+  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, M, below, T, k, nreal, nblk, mode, off,
+                     (const int32_t*)nullptr, (const int32_t*)nullptr);
+}
+
+void launch_band_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, const int32_t* li,
+                        const int32_t* lj, int64_t e0, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  const int T = (int)(M.ts / BLK);
+  const int64_t nblk = count * T * T;
+  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, M, below, T, k, nreal, nblk,
+                     (int)PAIRS_LIST, e0, li, lj);
 }
 
 void launch_panel(double* Dk, double* below, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k,

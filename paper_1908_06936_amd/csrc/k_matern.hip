@@ -57,7 +57,8 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 // block (u, v) of tile (I, J); blocks above the diagonal of a diagonal tile
 // are not needed by any later step and are skipped.  Mixed precision (tag !=
 // NULL): diagonal tiles FP64, off-diagonal tiles FP32 (tag 0) or BF16 (tag 1),
-// each rounded to nearest even from the FP64 value.
+// each rounded to nearest even from the FP64 value, or FP64 in the band pool
+// (tag 2).
 __global__ __launch_bounds__(256) void k_gen_tiles(TileMat M, int T, int64_t nreal, const double* __restrict__ xs,
                                                    const double* __restrict__ ys, const double* __restrict__ qt,
                                                    const double* __restrict__ cst, const uint8_t* __restrict__ tag,
@@ -76,12 +77,14 @@ __global__ __launch_bounds__(256) void k_gen_tiles(TileMat M, int T, int64_t nre
   const double xi = ipad ? 0.0 : xs[gi], yi = ipad ? 0.0 : ys[gi];
   const int64_t o = (u * BLK + r) + (int64_t)(v * BLK) * ts;  // element offset in the tile
   // 0: FP64, 1: FP32, 2: BF16
-  const int kind = (!tag || I == J) ? 0 : (tag[off_index(I, J, M.NT)] ? 2 : 1);
+  const int64_t idx = I == J ? 0 : off_index(I, J, M.NT);
+  const int tg = (!tag || I == J) ? -1 : tag[idx];
+  const int kind = (tg < 0 || tg == TAG_F64) ? 0 : (tg == TAG_BF16 ? 2 : 1);
   double* out64 = nullptr;
   float* out32 = nullptr;
   uint16_t* out16 = nullptr;
   if (kind == 0) {
-    out64 = (tag ? (I == J ? M.diag + I * ts * ts : nullptr) : tptr(M, I, J)) + o;
+    out64 = (tg == TAG_F64 ? band64(M, idx) : tptr(M, I, J)) + o;
   } else if (kind == 1) {
     out32 = (float*)M.off + off_index(I, J, M.NT) * ts * ts + o;
   } else {

@@ -2,7 +2,8 @@
 // tiles held in single or half precision, diagonal tiles in double).
 //
 // Storage: diagonal tiles FP64; off-diagonal tile (i, j) in a 4-byte slot per
-// entry, as FP32 (tag 0) or as BF16 in the first half of the slot (tag 1).
+// entry, as FP32 (tag 0) or as BF16 in the first half of the slot (tag 1), or,
+// for the FP64 band near the diagonal (tag 2), in a pool of FP64 tiles.
 // Step k of the factorisation:
 //   1. the column-k tiles below the diagonal are widened into an FP64 panel
 //      buffer, the panel is factored by the FP64 kernels and written back,
@@ -119,7 +120,9 @@ __global__ void k_panel_gather(TileMat M, int64_t k, const uint8_t* __restrict__
   const int64_t q = e / tt, o = e % tt;
   const int64_t idx = off_index(k + 1 + q, k, M.NT);
   const float* src = (const float*)M.off + idx * tt;
-  pbuf[e] = tag[idx] ? (double)bf16_to_f32(((const uint16_t*)src)[o]) : (double)src[o];
+  const int tg = tag[idx];
+  pbuf[e] = tg == TAG_F64 ? band64(M, idx)[o]
+                          : (tg == TAG_BF16 ? (double)bf16_to_f32(((const uint16_t*)src)[o]) : (double)src[o]);
 }
 
 // tile (k + 1 + q, k) = pbuf tile q rounded to nearest even in its precision;
@@ -134,7 +137,10 @@ __global__ void k_panel_scatter(TileMat M, int64_t k, const uint8_t* __restrict_
   float* dst = (float*)M.off + idx * tt;
   const float f = (float)pbuf[e];
   p32[e] = f;
-  if (tag[idx])
+  const int tg = tag[idx];
+  if (tg == TAG_F64)
+    band64(M, idx)[o] = pbuf[e];
+  else if (tg == TAG_BF16)
     ((uint16_t*)dst)[o] = f32_to_bf16(f);
   else
     dst[o] = f;
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(256) void k_panel_bf16t(const double* __restrict__ 
 // (p32 tile q holds L_{k+1+q, k}), so that a BF16-stored panel tile never
 // feeds its rounding error into targets near the diagonal; BF16 targets run
 // on BF16 MFMA with FP32 accumulation from the BF16 transposed panel copy pbt
-// (null when the step has no BF16 targets).  One 256-thread block computes
+// (null when the step has no BF16 targets); FP64 band targets are skipped.  One 256-thread block computes
 // one 128 x 128 block of a target tile.
 __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* __restrict__ tag,
                                                       const float* __restrict__ p32,
@@ -193,8 +199,10 @@ __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* 
   const int64_t i = k + 2 + a, j = k + 1 + c;
   if (i * ts + u * BLK >= nreal) return;  // padded rows: update is zero
   const int64_t ic = off_index(i, j, M.NT);
+  const int tg = tag[ic];
+  if (tg == TAG_F64) return;  // FP64 band target: updated by the FP64 kernel
   float* C = (float*)M.off + ic * tt;
-  if (tag[ic] && pbt) {
+  if (tg == TAG_BF16 && pbt) {
     v4f acc[4][4];
     accb_zero(acc);
     const uint16_t* A = pbt + (a + 1) * tt + (int64_t)u * BLK * ts;
@@ -220,7 +228,7 @@ __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* 
     acc32_zero(acc);
     gemm32_blk<SRC_F32, false, SRC_F32, false>(p32 + (a + 1) * tt + u * BLK, ts, p32 + c * tt + v * BLK, ts, (int)ts,
                                                 acc, (float*)smraw);
-    acc32_update(C, tag[ic] != 0, u * BLK + (int64_t)v * BLK * ts, ts, acc, -1.f);
+    acc32_update(C, tg == TAG_BF16, u * BLK + (int64_t)v * BLK * ts, ts, acc, -1.f);
   }
 }
 
@@ -242,8 +250,12 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_gemv_fwd_lp(TileMat M, const 
   __syncthreads();
   const int64_t idx = off_index(i, k, M.NT);
   const float* L = (const float*)M.off + idx * ts * ts;
+  const int tg = tag[idx];
   double s;
-  if (tag[idx]) {
+  if (tg == TAG_F64) {
+    const double* Ld = band64(M, idx) + u * BLK;
+    s = slab_rowdot([=](int r, int c) { return Ld[r + (int64_t)c * ts]; }, sy, (int)ts, red);
+  } else if (tg == TAG_BF16) {
     const uint16_t* Lh = (const uint16_t*)L + u * BLK;
     s = slab_rowdot([=](int r, int c) { return (double)bf16_to_f32(Lh[r + (int64_t)c * ts]); }, sy, (int)ts, red);
   } else {
@@ -265,8 +277,12 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_gemv_bwd_lp(TileMat M, const 
   const int64_t col0 = (cb % T) * BLK + 8 * (threadIdx.x >> 6);
   const int64_t idx = off_index(k, j, M.NT);
   const float* L = (const float*)M.off + idx * ts * ts;
+  const int tg = tag[idx];
   double s[8];
-  if (tag[idx]) {
+  if (tg == TAG_F64) {
+    const double* Ld = band64(M, idx);
+    wave_coldot8([=](int64_t r, int64_t c) { return Ld[r + c * ts]; }, ak, col0, false, ts, s);
+  } else if (tg == TAG_BF16) {
     const uint16_t* Lh = (const uint16_t*)L;
     wave_coldot8([=](int64_t r, int64_t c) { return (double)bf16_to_f32(Lh[r + c * ts]); }, ak, col0, false, ts, s);
   } else {
@@ -305,7 +321,10 @@ __global__ __launch_bounds__(256, 2) void k_tri_right_lp(TileMat M, const uint8_
     const float* A = (const float*)M.off + idx * tt;
     const double* B = Xk + v * BLK + off;
     const int K = (int)(ts - v * BLK);
-    if (tag[idx])
+    const int tg = tag[idx];
+    if (tg == TAG_F64)
+      gemm32_blk<SRC_F64, false, SRC_F64, true>(band64(M, idx) + u * BLK + off, ts, B, ts, K, acc, sm);
+    else if (tg == TAG_BF16)
       gemm32_blk<SRC_BF16, false, SRC_F64, true>((const uint16_t*)A + u * BLK + off, ts, B, ts, K, acc, sm);
     else
       gemm32_blk<SRC_F32, false, SRC_F64, true>(A + u * BLK + off, ts, B, ts, K, acc, sm);

@@ -63,6 +63,9 @@ void launch_trsv_fwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, 
 // an UpdatePart: all targets, the first trailing column, or the rest
 void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, bool diag_only, int part,
                         hipStream_t s);
+// mixed precision: FP64 update of the band tiles (li[e], lj[e]), e0 <= e < e0 + count
+void launch_band_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, const int32_t* li,
+                        const int32_t* lj, int64_t e0, int64_t count, hipStream_t s);
 void launch_panel(double* Dk, double* below, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k,
                   double* ldpart_k, unsigned long long* info, hipStream_t s);
 void launch_diag_inverses(double* Xd, const double* diag, const double* dinv, int64_t ts, int64_t NT, hipStream_t s);

@@ -1,0 +1,73 @@
+"""The C ABI on the host: the shared library loads, exports every entry point
+declared in include/exageo.h, and its host-only logic (workspace sizing,
+argument checks before any launch) behaves as documented.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "exageo.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(exageo_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1908_06936_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libexageo.so not built")
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("exageo_matern_cov", "exageo_loglik", "exageo_loglik_grad", "exageo_mle"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_binding_list_matches_header():
+    from paper_1908_06936_amd import _lib
+
+    assert sorted(_lib.EXPORTS) == declared_functions()
+
+
+def test_workspace_bytes_host_only(lib):
+    from paper_1908_06936_amd._lib import FP64, MIXED
+
+    ws = lib.exageo_workspace_bytes
+    assert ws(0, 768, FP64, 0) == 0  # invalid n
+    assert ws(1000, 100, FP64, 0) == 0  # ts not a multiple of 128
+    a = ws(40000, 768, FP64, 0)
+    g = ws(40000, 768, FP64, 1)
+    m = ws(40000, 768, MIXED, 0)
+    assert a > 0 and g > a
+    nt = (40000 + 767) // 768
+    tiles = nt * (nt + 1) // 2 * 768 * 768 * 8
+    assert tiles <= a < 1.3 * tiles  # the FP64 tiles dominate
+    assert m < 0.85 * a  # 4-byte off-diagonal slots (plus panel copies and the FP64 band pool)
+
+
+def test_entry_points_reject_bad_arguments_before_any_launch(lib):
+    from paper_1908_06936_amd._lib import EINVAL
+
+    out = ctypes.c_void_p()
+    assert lib.exageo_create(ctypes.byref(out), 0, 100, None) == EINVAL  # ts not a multiple of 128
+    assert lib.exageo_create(None, 0, 768, None) == EINVAL
+    ll = ctypes.c_double()
+    theta = (ctypes.c_double * 3)(1.0, 0.1, 0.5)
+    assert lib.exageo_loglik(None, 10, None, None, None, theta, 0, ctypes.byref(ll), None) == EINVAL
+    assert lib.exageo_set_mixed_policy(None, 3.0) == EINVAL
+    assert lib.exageo_set_mixed_fp64_band(None, 1.0) == EINVAL
+    assert lib.exageo_last_error(None) == b"null context"

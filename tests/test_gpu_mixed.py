@@ -169,3 +169,39 @@ def test_mixed_notpd_status(exa):
     ctx = exa.Context(ts=128)
     st, ll, info = ctx.loglik_status(dev([0.3, 0.3]), dev([0.2, 0.2]), dev([1.0, 0.5]), [4.0, 0.1, 0.5], "mixed")
     assert st == exa.ENOTPD and ll == -math.inf and info in (1, 2)
+
+
+def test_mixed_all_fp64_band_reproduces_fp64_bitwise(orc, exa):
+    # NT = 7: the band pool holds all 21 off-diagonal tiles, so every tile is
+    # FP64 and the mixed path runs the FP64 arithmetic in the same order
+    ctx = exa.Context(ts=256, band_factor=0.0, fp64_band=1e9)
+    x, y = inputgen.jittered_grid(40, seed=5)
+    th = [1.0, 0.1, 1.0]
+    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=5))
+    X, Y, Z = dev(x), dev(y), dev(z)
+    l64 = ctx.loglik(X, Y, Z, th, "fp64")
+    lmx = ctx.loglik(X, Y, Z, th, "mixed")
+    tm = ctx.timings()
+    assert tm["frac_fp64"] == 1.0 and tm["frac_bf16"] == 0.0
+    assert lmx == l64
+    assert l64 == pytest.approx(orc.loglik(x, y, z, th), rel=1e-10)
+
+
+@pytest.mark.parametrize("beta,nu", [(0.1, 0.5), (0.1, 1.0)])
+def test_mixed_fp64_band_reduces_error(orc, exa, beta, nu):
+    # 60 x 60 grid, ts 128: NT = 29; the pool holds 4 NT = 116 of the 406
+    # off-diagonal tiles, the closest ones
+    x, y = inputgen.jittered_grid(60, seed=6)
+    th = [1.0, beta, nu]
+    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=6))
+    ref = orc.loglik(x, y, z, th)
+    X, Y, Z = dev(x), dev(y), dev(z)
+    errs = {}
+    for fb in (0.0, 0.5):
+        ctx = exa.Context(ts=128, band_factor=0.0, fp64_band=fb)
+        st, got, _ = ctx.loglik_status(X, Y, Z, th, "mixed")
+        errs[fb] = (abs(got - ref) / abs(ref) if st == exa.OK else math.inf, ctx.timings()["frac_fp64"])
+    print(f"beta={beta} nu={nu}: " + ", ".join(f"fp64 band {b}: rel {e:.2e} (fp64 tiles {f:.2f})"
+                                               for b, (e, f) in errs.items()))
+    assert errs[0.0][1] == 0.0 and 0.0 < errs[0.5][1] <= 116 / 406 + 1e-12
+    assert errs[0.5][0] < errs[0.0][0]
