@@ -119,7 +119,9 @@ def mle_study(args) -> int:
         ctx, X, Y, Z = field(200, th_true, 1, 768)
         runs = {}
         for label, meth, prec, cap in (("fp64_dfo", "dfo", "fp64", 400), ("fp64_lbfgsb", "lbfgsb", "fp64", 80),
-                                       ("mixed_lbfgsb", "lbfgsb", "mixed", 80)):
+                                       ("mixed_lbfgsb", "lbfgsb", "mixed", 80), ("mixed_dfo", "dfo", "mixed", 400)):
+            # mixed: FP32 off-diagonal tiles with the FP64 band at 0.5 beta, no BF16
+            ctx.set_mixed_policy(0.0, 0.5)
             t0 = time.perf_counter()
             try:
                 th_hat, l_hat, st = ctx.mle(X, Y, Z, lb, ub, theta0=th0, tol=1e-4, max_iters=cap, method=meth,
@@ -130,7 +132,8 @@ def mle_study(args) -> int:
             wall = time.perf_counter() - t0
             l64 = ctx.loglik_status(X, Y, Z, th_hat, "fp64")[1]
             runs[label] = {"theta_hat": th_hat, "loglik_reported": l_hat, "loglik_fp64_at_theta_hat": l64,
-                           "wall_s": wall, "max_evals": cap, "stats": st}
+                           "wall_s": wall, "max_evals": cap, "stats": st,
+                           "mixed_policy": "FP32 off-diagonal, FP64 band 0.5 beta" if prec == "mixed" else None}
             print(f"[mle] n=40000 nu={th_true[2]} {label}: {wall:.1f} s, theta {th_hat}, {st}", file=sys.stderr,
                   flush=True)
         ref = runs.get("fp64_dfo", {}).get("loglik_fp64_at_theta_hat")
@@ -148,7 +151,8 @@ def mle_study(args) -> int:
     # large n: single evaluations
     m = args.big_n_side
     ctx, X, Y, Z = field(m, th_true, 2, 768)
-    big = {"n": m * m}
+    ctx.set_mixed_policy(0.0, 0.5)
+    big = {"n": m * m, "mixed_policy": "FP32 off-diagonal, FP64 band 0.5 beta"}
     for label, prec, grad in (("fp64_loglik", "fp64", False), ("fp64_loglik_grad", "fp64", True),
                               ("mixed_loglik_grad", "mixed", True)):
         torch.cuda.synchronize()

@@ -90,7 +90,7 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
   p.off_box = take(8 * 8);
   p.off_qt = take((size_t)QNB * QNK * QW * 8);
   p.off_cst = take(8 * 8);
-  p.off_part = take((size_t)(p.grad ? exg::lauum_blocks(ts, p.NT) : 1) * 3 * 8);
+  p.off_part = take((size_t)(p.grad ? exg::lauum_blocks(ts, p.NT) + p.pool_cap * p.T * p.T : 1) * 3 * 8);
   p.off_out = take(16 * 8);
   p.off_info = take(8);
   p.bytes = o;
@@ -447,6 +447,7 @@ exageo_status gradient(exageo_ctx* c, const Plan& p) {
   double* rhs = at<double>(c, p.off_av);
   double* av = at<double>(c, p.off_alpha);
   double* Xd = at<double>(c, p.off_xd);
+  int64_t nparts = exg::lauum_blocks(p.ts, p.NT);  // partial triples of the contraction
   // a = Sigma^-1 z = L^-T y
   exg::launch_copy(rhs, at<double>(c, p.off_y), p.npad, c->stream);
   if (p.mixed) {
@@ -455,9 +456,10 @@ exageo_status gradient(exageo_ctx* c, const Plan& p) {
     exg::launch_trsv_bwd_lp(M, tag, Xd, rhs, av, c->stream);
     for (int64_t k = 0; k < p.NT; ++k)
       exg::launch_trtri_step_lp(M, tag, Xd + k * p.ts * p.ts, at<float>(c, p.off_p32), k, p.n, c->stream);
-    exg::launch_lauum_contract_lp(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
-                                  at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part),
-                                  c->stream);
+    nparts = exg::launch_lauum_contract_lp(M, tag, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
+                                           at<double>(c, p.off_qt), at<double>(c, p.off_cst),
+                                           at<int32_t>(c, p.off_bli), at<int32_t>(c, p.off_blj), c->bfirst[p.NT],
+                                           at<double>(c, p.off_part), c->stream);
   } else {
     exg::launch_trsv_bwd(M, Xd, rhs, av, c->stream);
     // L^-1 in place, then the fused LAUUM + contraction
@@ -467,8 +469,7 @@ exageo_status gradient(exageo_ctx* c, const Plan& p) {
                                at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part),
                                c->stream);
   }
-  exg::launch_finalize_grad(at<double>(c, p.off_part), exg::lauum_blocks(p.ts, p.NT), at<double>(c, p.off_out) + 3,
-                            c->stream);
+  exg::launch_finalize_grad(at<double>(c, p.off_part), nparts, at<double>(c, p.off_out) + 3, c->stream);
   HIPCHK(c, hipGetLastError());
   rec(c, 5);
   return EXAGEO_OK;

@@ -381,13 +381,14 @@ __global__ void k_copy_back_lp(TileMat M, const float* __restrict__ P, int64_t c
 }
 
 // ------------------------------------ mixed fused LAUUM + score contraction
-// X = L^-1 has FP64 diagonal tiles and FP32 off-diagonal tiles.  Off-diagonal
-// blocks W_IJ (I > J) run on FP32 MFMA with FP32 accumulation; diagonal
-// blocks W_II on FP64 MFMA (FP32 tiles widened exactly), so that the
-// precision map of W is that of Sigma.  The contraction is FP64 in both.
-// Off-diagonal kernel: pair p -> (a, c), c <= a, I = a + 1 > J = c.
-__global__ __launch_bounds__(256, 2) void k_lauum_contract_lp(TileMat M, int T, int64_t nreal,
-                                                              const double* __restrict__ xs,
+// X = L^-1 has FP64 diagonal tiles and FP32 off-diagonal tiles.  W follows the
+// precision map of Sigma: blocks W_IJ of FP32 and BF16 tiles run on FP32 MFMA
+// with FP32 accumulation; diagonal blocks W_II and the blocks of FP64 band
+// tiles run on FP64 MFMA (FP32 tiles widened exactly), where the entries of
+// dSigma are largest.  The contraction is FP64 in both.
+// FP32 kernel: pair p -> (a, c), c <= a, I = a + 1 > J = c; band tiles skipped.
+__global__ __launch_bounds__(256, 2) void k_lauum_contract_lp(TileMat M, const uint8_t* __restrict__ tag, int T,
+                                                              int64_t nreal, const double* __restrict__ xs,
                                                               const double* __restrict__ ys,
                                                               const double* __restrict__ av,
                                                               const double* __restrict__ qt,
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract_lp(TileMat M, int T, 
   int64_t a, c;
   tri_decode(p, &a, &c);
   const int64_t I = a + 1, J = c;
-  if (I * ts + u * BLK >= nreal || J * ts + v * BLK >= nreal) {
+  if (tag[off_index(I, J, NT)] == TAG_F64 || I * ts + u * BLK >= nreal || J * ts + v * BLK >= nreal) {
     if (threadIdx.x < 3) part[3 * b + threadIdx.x] = 0.0;
     return;
   }
@@ -422,22 +423,24 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract_lp(TileMat M, int T, 
   contract_block32(acc, I * ts + r0, J * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
 }
 
-// Diagonal kernel: block (I, I, u, v), v <= u, on FP64 MFMA.
-__global__ __launch_bounds__(256, 2) void k_lauum_diag_lp(TileMat M, int T, int64_t nreal,
-                                                          const double* __restrict__ xs,
-                                                          const double* __restrict__ ys,
-                                                          const double* __restrict__ av,
-                                                          const double* __restrict__ qt,
-                                                          const double* __restrict__ cst, double* __restrict__ part,
-                                                          int64_t nb) {
+// FP64 kernel: block (I, J, u, v) with (I, J) = the diagonal tile p for
+// p < NT, else band tile (li, lj)[p - NT]; v <= u on the diagonal.
+__global__ __launch_bounds__(256, 2) void k_lauum_f64_lp(TileMat M, int T, int64_t nreal, const double* __restrict__ xs,
+                                                         const double* __restrict__ ys,
+                                                         const double* __restrict__ av,
+                                                         const double* __restrict__ qt,
+                                                         const double* __restrict__ cst, double* __restrict__ part,
+                                                         int64_t nb, const int32_t* __restrict__ li,
+                                                         const int32_t* __restrict__ lj) {
   __shared__ double sm[GEMM_LDS];
   const int64_t ts = M.ts, NT = M.NT;
   const int64_t b = blockIdx.x;
   if (b >= nb) return;
-  const int64_t I = b / (T * T);
+  const int64_t p = b / (T * T);
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
-  if (u < v || I * ts + u * BLK >= nreal || I * ts + v * BLK >= nreal) {
+  const int64_t I = p < NT ? p : li[p - NT], J = p < NT ? p : lj[p - NT];
+  if ((I == J && u < v) || I * ts + u * BLK >= nreal || J * ts + v * BLK >= nreal) {
     if (threadIdx.x < 3) part[3 * b + threadIdx.x] = 0.0;
     return;
   }
@@ -445,13 +448,18 @@ __global__ __launch_bounds__(256, 2) void k_lauum_diag_lp(TileMat M, int T, int6
   acc_zero(acc);
   const int64_t r0 = (int64_t)u * BLK, c0 = (int64_t)v * BLK;
   const double* XII = M.diag + I * ts * ts;
-  gemm_blk<true, true>(XII + r0 + r0 * ts, ts, XII + r0 + c0 * ts, ts, (int)(ts - r0), acc, sm);
+  if (I == J)
+    gemm_blk<true, true>(XII + r0 + r0 * ts, ts, XII + r0 + c0 * ts, ts, (int)(ts - r0), acc, sm);
+  else
+    gemm_core<true, true>([=](int k0) -> const double* { return XII + r0 + k0 + r0 * ts; }, ts,
+                          [=](int k0) -> const float* { return off32(M, I, J) + r0 + k0 + c0 * ts; }, ts,
+                          (int)(ts - r0), acc, sm);
   if (I + 1 < NT) {
     auto ap = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, I) + (k0 % ts) + r0 * ts; };
-    auto bp = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, I) + (k0 % ts) + c0 * ts; };
+    auto bp = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, J) + (k0 % ts) + c0 * ts; };
     gemm_core<true, true>(ap, ts, bp, ts, (int)((NT - 1 - I) * ts), acc, sm);
   }
-  contract_block64(acc, I * ts + r0, I * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
+  contract_block64(acc, I * ts + r0, J * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -550,17 +558,20 @@ void launch_trtri_step_lp(const TileMat& M, const uint8_t* tag, const double* Xk
   launch_copy(M.diag + k * tt, Xk, tt, s);
 }
 
-// part: lauum_blocks(ts, NT) triples, the off-diagonal blocks first
-void launch_lauum_contract_lp(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* av,
-                              const double* qt, const double* cst, double* part, hipStream_t s) {
+// part: lauum_blocks(ts, NT) + nband T^2 triples, the FP32 blocks first;
+// returns the number of triples written
+int64_t launch_lauum_contract_lp(const TileMat& M, const uint8_t* tag, int64_t nreal, const double* xs,
+                                 const double* ys, const double* av, const double* qt, const double* cst,
+                                 const int32_t* li, const int32_t* lj, int64_t nband, double* part, hipStream_t s) {
   const int T = (int)(M.ts / BLK);
   const int64_t NT = M.NT;
-  const int64_t nb_off = NT * (NT - 1) / 2 * T * T, nb_diag = NT * T * T;
+  const int64_t nb_off = NT * (NT - 1) / 2 * T * T, nb64 = (NT + nband) * T * T;
   if (nb_off > 0)
-    hipLaunchKernelGGL(k_lauum_contract_lp, dim3((unsigned)nb_off), dim3(256), 0, s, M, T, nreal, xs, ys, av, qt, cst,
-                       part, nb_off);
-  hipLaunchKernelGGL(k_lauum_diag_lp, dim3((unsigned)nb_diag), dim3(256), 0, s, M, T, nreal, xs, ys, av, qt, cst,
-                     part + 3 * nb_off, nb_diag);
+    hipLaunchKernelGGL(k_lauum_contract_lp, dim3((unsigned)nb_off), dim3(256), 0, s, M, tag, T, nreal, xs, ys, av, qt,
+                       cst, part, nb_off);
+  hipLaunchKernelGGL(k_lauum_f64_lp, dim3((unsigned)nb64), dim3(256), 0, s, M, T, nreal, xs, ys, av, qt, cst,
+                     part + 3 * nb_off, nb64, li, lj);
+  return nb_off + nb64;
 }
 
 }  // namespace exg

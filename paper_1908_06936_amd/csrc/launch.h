@@ -53,8 +53,10 @@ void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, 
 // one step of the mixed inverse (FP32 off-diagonal tiles of L^-1, FP32 buffer P)
 void launch_trtri_step_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k, int64_t nreal,
                           hipStream_t s);
-void launch_lauum_contract_lp(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* av,
-                              const double* qt, const double* cst, double* part, hipStream_t s);
+// mixed fused LAUUM + contraction; returns the number of partial triples
+int64_t launch_lauum_contract_lp(const TileMat& M, const uint8_t* tag, int64_t nreal, const double* xs,
+                                 const double* ys, const double* av, const double* qt, const double* cst,
+                                 const int32_t* li, const int32_t* lj, int64_t nband, double* part, hipStream_t s);
 void launch_trsv_fwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, int64_t nreal, double* rhs,
                         double* y, hipStream_t s);
 

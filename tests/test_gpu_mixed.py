@@ -205,3 +205,23 @@ def test_mixed_fp64_band_reduces_error(orc, exa, beta, nu):
                                                for b, (e, f) in errs.items()))
     assert errs[0.0][1] == 0.0 and 0.0 < errs[0.5][1] <= 116 / 406 + 1e-12
     assert errs[0.5][0] < errs[0.0][0]
+
+
+def test_mixed_grad_fp64_band_vs_oracle(orc, exa):
+    # the FP64 band also sets the precision of the matching blocks of
+    # Sigma^-1 (and of L): the score error drops against the FP32-only policy
+    x, y = inputgen.jittered_grid(60, seed=6)
+    th = [1.0, 0.1, 0.5]
+    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=6))
+    gref = np.asarray(orc.loglik_grad(x, y, z, th)[1])
+    X, Y, Z = dev(x), dev(y), dev(z)
+    errs = {}
+    for fb in (0.0, 0.5):
+        ctx = exa.Context(ts=128, band_factor=0.0, fp64_band=fb)
+        g = np.asarray(ctx.loglik_grad(X, Y, Z, th, "mixed")[1])
+        errs[fb] = (np.abs(g - gref) / np.abs(gref).max()).max()
+    print(f"mixed score error / max|g|: FP32 only {errs[0.0]:.2e}, FP64 band 0.5 beta {errs[0.5]:.2e}")
+    # measured 3.6e-6 and 2.8e-6: the band removes the largest terms of W's
+    # error; the FP32 inverse factor outside it keeps the rest
+    assert errs[0.5] < errs[0.0]
+    assert errs[0.5] <= 1e-5
