@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a plain 1 GiB
 # device copy read and write 1 GiB.  Valid only for the kernel sources the
 # counters were taken on (fingerprint below); otherwise reported as null.
-TRAFFIC_BYTES_PER_LAUNCH = (9.942e6 * 2.0 + 2.047e6 * 1.0) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = (4.9503e6 * 2.0 + 1.0333e6 * 1.0) * 1024
 TRAFFIC_SOURCES = ("paper_1908_06936_amd/csrc/common.h", "paper_1908_06936_amd/csrc/k_gemm.hip")
-TRAFFIC_FINGERPRINT = "adfbc0efbebe41a9c2ac4a023a422f82d9bbbbe7"
+TRAFFIC_FINGERPRINT = "49435b141208c34851a45e161e7e31b1eaacc790"
 
 
 def traffic_bytes():
@@ -186,6 +186,8 @@ def main() -> int:
     ap.add_argument("--ts", type=int, default=768)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=1500)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the l-only and FP64-vs-mixed sections (profiling runs of the headline step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--mle-study", action="store_true",
@@ -286,6 +288,11 @@ def main() -> int:
         "loglik": lls[-1][0],
         "grad": lls[-1][1],
     }
+    if args.no_mixed:
+        if not args.no_cpu:
+            result["cpu_baseline"] = cpu_baseline(n, theta, args.cpu_sample)
+        print(json.dumps(result))
+        return 0
     # l(theta) alone, FP64 and mixed precision (FP64 diagonal tiles, FP32
     # off-diagonal tiles; BF16 beyond band * beta), same inputs (the smooth
     # nu = 1 field on uniform points is too ill-conditioned for FP32 tiles:
