@@ -172,6 +172,22 @@ def simulate(x, y, theta, e) -> np.ndarray:
     return z
 
 
+def dense_factor_lapack(x, y, theta) -> np.ndarray:
+    """Lower Cholesky factor of the oracle's own dense Sigma(theta) (eq. 3) by
+    LAPACK (numpy): the plain definition with a library factorisation as a
+    step, for the full-size checks where the unblocked O(n^3) loop is slow."""
+    return np.linalg.cholesky(matern_cov(x, y, theta))
+
+
+def loglik_from_factor(L: np.ndarray, z) -> float:
+    """eq. (2) from a lower Cholesky factor: -(n ln 2 pi + 2 sum ln L_ii + |L^-1 z|^2) / 2."""
+    import scipy.linalg
+
+    z = _f64(z)
+    v = scipy.linalg.solve_triangular(L, z, lower=True)
+    return -0.5 * (z.size * np.log(2.0 * np.pi) + 2.0 * np.log(np.diag(L)).sum() + v @ v)
+
+
 def loglik(x, y, z, theta, *, details: bool = False):
     """l(theta) of eq. (2); raises OracleError on invalid input / non-PD."""
     x, y, z, th = _f64(x), _f64(y), _f64(z), _f64(theta)

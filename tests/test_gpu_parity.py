@@ -89,6 +89,19 @@ def test_loglik_jittered_grid_vs_oracle(orc, ctx256, beta, nu):
     assert got == pytest.approx(ref, rel=1e-10)
 
 
+def test_loglik_config2_full_size(orc, exa):
+    # n = 10,000 (100 x 100 jittered grid), tile 512 (NT = 20, last tile 272):
+    # against the oracle's own covariance factored by LAPACK
+    x, y = inputgen.jittered_grid(100, seed=0)
+    th = [1.0, 0.1, 1.0]
+    L = orc.dense_factor_lapack(x, y, th)
+    z = L @ inputgen.normals(x.size, seed=0)
+    ref = orc.loglik_from_factor(L, z)
+    ctx = exa.Context(ts=512)
+    got = ctx.loglik(dev(x), dev(y), dev(z), th)
+    assert got == pytest.approx(ref, rel=1e-10)
+
+
 def test_loglik_worked_values(exa):
     ctx = exa.Context(ts=128)
     assert ctx.loglik(dev([0.0]), dev([0.0]), dev([0.7]), [2, 0.1, 0.5]) == pytest.approx(-1.3880121234846454,

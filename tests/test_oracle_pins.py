@@ -378,3 +378,15 @@ def test_mle_interior_stationary(orc):
     # sigma^2 at the maximiser is the profile value q_R(beta, nu) / n
     _, _, q_r = orc.loglik(x, y, z, [1.0, th[1], th[2]], details=True)
     assert th[0] == pytest.approx(q_r / x.size, rel=1e-3)
+
+
+def test_lapack_factor_path_matches_unblocked_oracle(orc):
+    # the full-size helper (oracle covariance + library Cholesky) agrees with
+    # the oracle's own unblocked factorisation on a case both can do
+    import inputgen
+
+    x, y = inputgen.jittered_grid(15, seed=3)
+    th = [1.3, 0.08, 0.9]
+    z = inputgen.normals(x.size, seed=3)
+    L = orc.dense_factor_lapack(x, y, th)
+    assert orc.loglik_from_factor(L, z) == pytest.approx(orc.loglik(x, y, z, th), rel=1e-12)
