@@ -285,6 +285,11 @@ def main() -> int:
         "potrf_frac_of_fp64_mfma_peak": chol_tflops / FP64_MFMA_PEAK_TFLOPS,
         "phases_ms": {k: avg(k) for k in ("prep_ms", "gen_ms", "chol_ms", "solve_ms", "grad_ms", "total_ms")},
         "gen_bessel_evals_per_s": (n * (n + 1) / 2) / (avg("gen_ms") * 1e-3),
+        # generation writes the lower tiles once; the forward solve reads them once
+        "gen_hbm_write_gbs": ((n + ts - 1) // ts) * (((n + ts - 1) // ts) + 1) / 2 * ts * ts * 8
+                             / (avg("gen_ms") * 1e-3) / 1e9,
+        "solve_hbm_read_gbs": ((n + ts - 1) // ts) * (((n + ts - 1) // ts) + 1) / 2 * ts * ts * 8
+                              / (avg("solve_ms") * 1e-3) / 1e9,
         "loglik": lls[-1][0],
         "grad": lls[-1][1],
     }
@@ -339,19 +344,30 @@ def main() -> int:
             if st != 0:
                 grid[key][label] = {"status": exa.STATUS_NAMES.get(st, st), "info": info}
                 continue
+            ctx.set_profiling(True)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             for _ in range(args.steps):
                 v = ctx.loglik(Xg, Yg, Zg, th_g, prec)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
+            tm = ctx.timings()
+            ctx.set_profiling(False)
             for _ in range(args.steps):
                 lg, gg = ctx.loglik_grad(Xg, Yg, Zg, th_g, prec)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
+            # trailing update: achieved rate against the peak weighted by the
+            # precision of its flops, 1 / sum(share_p / peak_p)
+            fl = [tm["update_flops_fp32"], tm["update_flops_bf16"], tm["update_flops_fp64"]]
+            wpeak = sum(fl) / sum(f / pk for f, pk in zip(fl, (157.3, 2500.0, FP64_MFMA_PEAK_TFLOPS)))
+            upd = tm["update_flops"] / (tm["update_kernel_ms"] * 1e-3) / 1e12
             grid[key][label] = {"status": "OK", "loglik_evals_per_s": args.steps / (t2 - t1),
                                 "loglik_grad_evals_per_s": args.steps / (t3 - t2), "loglik": v, "grad": gg,
-                                "frac_bf16_tiles": ctx.timings().get("frac_bf16")}
+                                "frac_bf16_tiles": tm.get("frac_bf16"),
+                                "update_flop_shares_fp32_bf16_fp64": [f / sum(fl) for f in fl],
+                                "update_tflops": upd, "update_weighted_peak_tflops": wpeak,
+                                "update_frac_of_weighted_peak": upd / wpeak}
         ref = grid[key]["fp64"]
         for label, d in grid[key].items():
             if label != "fp64" and "loglik" in d and "loglik" in ref:

@@ -165,7 +165,9 @@ exageo_status exageo_mle(exageo_ctx *ctx, int64_t n, const double *x, const doub
  *   FP64 equivalent), 9 number of FP64 trailing-update (k_chol_update)
  *   launches, 10 precision used, 11 fraction of off-diagonal tiles in BF16,
  *   12 fraction in FP32, 13 number of factorisation steps with an update,
- *   14 fraction of off-diagonal tiles in the FP64 band.
+ *   14 fraction of off-diagonal tiles in the FP64 band, 15 / 16 / 17
+ *   trailing-update flops into FP32 / BF16 / FP64 targets (the last includes
+ *   the diagonal tiles; FP64 mode counts everything there).
  * Returns the number of values written. */
 int exageo_get_timings(const exageo_ctx *ctx, double *out, int nmax);
 exageo_status exageo_set_profiling(exageo_ctx *ctx, int on);

@@ -138,11 +138,11 @@ class Context:
         self._check(self._lib.exageo_set_profiling(self._h, int(on)), "set_profiling")
 
     def timings(self) -> dict:
-        buf = (ctypes.c_double * 16)()
-        m = self._lib.exageo_get_timings(self._h, buf, 16)
+        buf = (ctypes.c_double * 24)()
+        m = self._lib.exageo_get_timings(self._h, buf, 24)
         keys = ["total_ms", "prep_ms", "gen_ms", "chol_ms", "update_kernel_ms", "update_flops", "solve_ms",
                 "grad_ms", "chol_flops", "update_launches", "precision", "frac_bf16", "frac_fp32", "update_steps",
-                "frac_fp64"]
+                "frac_fp64", "update_flops_fp32", "update_flops_bf16", "update_flops_fp64"]
         return {k: buf[i] for i, k in enumerate(keys[:m])}
 
     # ---------------------------------------------------------- operations

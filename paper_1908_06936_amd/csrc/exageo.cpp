@@ -19,7 +19,6 @@
 namespace {
 
 constexpr int64_t BLKH = 128;
-constexpr int QNB = 10, QNK = 192, QW = 5;  // quadrature table (matern_dev.h)
 constexpr int NEV = 512;                     // profiling events
 constexpr int64_t kBandPoolPerColumn = 4;    // FP64 band pool size, tiles per tile column
 
@@ -88,7 +87,7 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
   p.off_perm = take((size_t)p.npad * 4);
   p.off_keys = take((size_t)p.P * 8);
   p.off_box = take(8 * 8);
-  p.off_qt = take((size_t)QNB * QNK * QW * 8);
+  p.off_qt = take((size_t)exg::quad_table_doubles() * 8);
   p.off_cst = take(8 * 8);
   p.off_part = take((size_t)(p.grad ? exg::lauum_blocks(ts, p.NT) + p.pool_cap * p.T * p.T : 1) * 3 * 8);
   p.off_out = take(16 * 8);
@@ -131,7 +130,7 @@ struct exageo_ctx {
   // profiling
   hipEvent_t ev[NEV];
   int nev_created = 0;
-  double timings[16] = {0};
+  double timings[24] = {0};
 };
 
 namespace {
@@ -351,6 +350,7 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
                         at<double>(c, p.off_cst), tag, c->stream);
   rec(c, 2);
   double upd_flops = 0.0;
+  double flops_by[3] = {0.0, 0.0, 0.0};  // FP32, BF16, FP64 targets
   int nupd = 0;
   // Lookahead of one panel: step k first updates the first trailing column
   // (k + 1) on the main stream; the side stream then factors panel k + 1
@@ -406,19 +406,26 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
     HIPCHK(c, hipStreamWaitEvent(S, c->ev_panel, 0));
     below = next;
     nupd += p.NT - k - 1 >= 2 ? 2 : 1;  // launches of k_chol_update in this step
-    // algorithmic flops of this update over the real rows
+    // algorithmic flops of this update over the real rows, by target precision
     for (int64_t j = k + 1; j < p.NT; ++j) {
       const double rj = (double)std::min<int64_t>(p.ts, p.n - j * p.ts);
       upd_flops += rj * (rj + 1.0) * (double)p.ts;  // SYRK
+      flops_by[2] += rj * (rj + 1.0) * (double)p.ts;
       for (int64_t i = j + 1; i < p.NT; ++i) {
         const double ri = (double)std::min<int64_t>(p.ts, p.n - i * p.ts);
-        upd_flops += 2.0 * ri * rj * (double)p.ts;
+        const double f = 2.0 * ri * rj * (double)p.ts;
+        upd_flops += f;
+        const int tg = p.mixed ? c->htag[exg::off_index(i, j, p.NT)] : (int)exg::TAG_F64;
+        flops_by[tg == exg::TAG_F64 ? 2 : (tg == exg::TAG_BF16 ? 1 : 0)] += f;
       }
     }
   }
   HIPCHK(c, hipGetLastError());
   rec(c, 3);
   c->timings[5] = upd_flops;
+  c->timings[15] = flops_by[0];
+  c->timings[16] = flops_by[1];
+  c->timings[17] = flops_by[2];
   c->timings[9] = nupd;
   c->timings[13] = (double)std::max<int64_t>(0, p.NT - 1);
   return EXAGEO_OK;
@@ -617,7 +624,7 @@ exageo_status exageo_set_profiling(exageo_ctx* c, int on) {
 
 int exageo_get_timings(const exageo_ctx* c, double* out, int nmax) {
   if (!c || !out) return 0;
-  int m = nmax < 16 ? nmax : 16;
+  int m = nmax < 24 ? nmax : 24;
   for (int i = 0; i < m; ++i) out[i] = c->timings[i];
   return m;
 }

@@ -25,7 +25,7 @@ __device__ double dev_digamma(double z) {
 // integrands including the trapezoidal end weight h/2 at t = 0.
 __global__ void k_quad_table(double s2, double beta, double nu, double* __restrict__ qt, double* __restrict__ cst) {
   const int m = blockIdx.x, k = threadIdx.x;
-  const double h = 0.2 * exp2(-0.5 * m);
+  const double h = 0.1 * exp2(-0.5 * m);
   const double t = k * h;
   const double sh = sinh(0.5 * t);
   const double w = (k == 0) ? 0.5 * h : h;
@@ -43,6 +43,41 @@ __global__ void k_quad_table(double s2, double beta, double nu, double* __restri
     cst[C_C] = c;
     cst[C_PSI] = dev_digamma(nu);
     cst[C_S2C] = s2 * c;
+  }
+}
+
+// Tables of u0, u1, u2 on segment blockIdx.x of ln x (see matern_dev.h): the
+// functions at the 13 Chebyshev points by the quadrature; stored per function
+// are its value at the segment centre (the middle point, t = 0) and the
+// Chebyshev coefficients of ln(u / u_centre), c_k = (2/N) sum_j d_j
+// cos(pi k (j + 1/2) / N), whose magnitudes stay small.  Runs after
+// k_quad_table.
+__global__ __launch_bounds__(64) void k_cheb_table(double* __restrict__ qt, const double* __restrict__ cst) {
+  __shared__ double fv[3][CH_N];
+  const int seg = blockIdx.x, j = threadIdx.x;
+  const double nu = cst[C_NU];
+  if (j < CH_N) {
+    const double tj = cos(3.14159265358979323846 * (j + 0.5) / CH_N);
+    const double x = exp(CH_SLO + (seg + 0.5 * (tj + 1.0)) * CH_DS);
+    double t0, t1, t2;
+    quad_k3(qt, x, nu, &t0, &t1, &t2);
+    const double xn = pow(x, nu);
+    fv[0][j] = xn * t0;
+    fv[1][j] = xn * x * t1;
+    fv[2][j] = xn * t2;
+  }
+  __syncthreads();
+  if (j < 3 * 16) {
+    const int f = j >> 4, k = j & 15;
+    double c = 0.0;
+    if (k < CH_N) {
+      for (int q = 0; q < CH_N; ++q)
+        c += log(fv[f][q] / fv[f][CH_MID]) * cos(3.14159265358979323846 * k * (q + 0.5) / CH_N);
+      c *= 2.0 / CH_N;
+    } else if (k == CH_N) {
+      c = fv[f][CH_MID];
+    }
+    qt[QT_CHEB_OFF + seg * CH_STRIDE + f * 16 + k] = c;
   }
 }
 
@@ -119,8 +154,12 @@ __global__ __launch_bounds__(256) void k_gen_dense(double* __restrict__ cov, int
   }
 }
 
+int64_t quad_table_doubles() { return QT_TOTAL; }
+
+// qt: QT_TOTAL doubles (quadrature nodes, then the Chebyshev tables)
 void launch_quad_table(const double theta[3], double* qt, double* cst, hipStream_t s) {
   hipLaunchKernelGGL(k_quad_table, dim3(QNB), dim3(QNK), 0, s, theta[0], theta[1], theta[2], qt, cst);
+  hipLaunchKernelGGL(k_cheb_table, dim3(CH_NSEG), dim3(64), 0, s, qt, (const double*)cst);
 }
 
 void launch_gen_tiles(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* qt,

@@ -65,6 +65,22 @@ def test_matern_cov_small_and_large_distances(orc, ctx256):
         assert np.all(err <= 2e-13 * np.abs(ref) + 1e-250)
 
 
+@pytest.mark.parametrize("nu", [0.01, 0.3, 1.0, 2.5, 7.5, 12.0])
+def test_matern_cov_across_interpolation_segments(orc, ctx256, nu):
+    # x = r / beta log-spaced from 1e-12 (below the interpolation tables, where
+    # the quadrature is used directly) to 800 (past the cut to zero), about
+    # six points per table segment of ln x
+    t = np.concatenate([[0.0], np.logspace(-12, np.log10(800.0), 700)])
+    x, y = t, np.zeros_like(t)
+    th = [0.7, 1.0, nu]
+    ref = orc.matern_cov(x, y, th)[0]
+    got = ctx256.matern_cov(dev(x), dev(y), th).cpu().numpy()[0]
+    err = np.abs(got - ref)
+    big = np.abs(ref) > 1e-250
+    print(f"nu={nu}: max rel err {np.max(err[big] / np.abs(ref[big])):.2e} (entries above 1e-250)")
+    assert np.all(err <= 2e-13 * np.abs(ref) + 1e-250)
+
+
 # ------------------------------------------------------------ likelihood
 @pytest.mark.parametrize("n,ts,nu", [(1, 256, 0.5), (7, 128, 1.0), (300, 128, 0.5), (1000, 256, 1.0),
                                      (1500, 128, 1.7), (2100, 512, 0.8)])
