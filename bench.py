@@ -177,6 +177,49 @@ def mle_study(args) -> int:
     return 0
 
 
+def precision_study(args) -> int:
+    """l in FP64 and in mixed precision at n = 90,000 (300 x 300 jittered grid,
+    theta = (1, beta, 0.5), beta in {0.03, 0.1}, tile 768): relative
+    difference, wall clock and tile fractions for FP32 off-diagonal tiles,
+    FP32 with an FP64 band of 0.5 beta, and BF16 beyond 3 beta (one JSON line)."""
+    import torch
+
+    import inputgen
+    import paper_1908_06936_amd as exa
+
+    dev = torch.device("cuda:0")
+    x, y = inputgen.jittered_grid(300, seed=0)
+    e = inputgen.normals(x.size, seed=0)
+    X, Y, E = (torch.as_tensor(a, device=dev) for a in (x, y, e))
+    ctx = exa.Context(ts=768)
+    out = {"study": "precision", "n": int(x.size), "data": "synthetic", "grid": "300x300 jittered, seed 0"}
+    for beta in (0.03, 0.1):
+        th = [1.0, beta, 0.5]
+        Z = ctx.simulate(X, Y, th, E)
+        res = {}
+        for label, prec, bf, f64 in (("fp64", "fp64", 3.0, 0.0), ("mixed_fp32", "mixed", 0.0, 0.0),
+                                     ("mixed_fp32_fp64band", "mixed", 0.0, 0.5), ("mixed_bf16_3beta", "mixed", 3.0, 0.0),
+                                     ("mixed_bf16_3beta_fp64band", "mixed", 3.0, 0.5)):
+            ctx.set_mixed_policy(bf, f64)
+            ctx.loglik_status(X, Y, Z, th, prec)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, v, info = ctx.loglik_status(X, Y, Z, th, prec)
+            torch.cuda.synchronize()
+            tm = ctx.timings()
+            res[label] = {"status": exa.STATUS_NAMES.get(st, st), "loglik": v, "s": time.perf_counter() - t0,
+                          "frac_bf16": tm.get("frac_bf16"), "frac_fp64_band": tm.get("frac_fp64")}
+            print(f"[precision] beta={beta} {label}: {res[label]}", file=sys.stderr, flush=True)
+        l64 = res["fp64"]["loglik"]
+        for d in res.values():
+            if d["status"] == "OK":
+                d["rel_dl_vs_fp64"] = abs(d["loglik"] - l64) / abs(l64)
+                d["speedup_vs_fp64"] = res["fp64"]["s"] / d["s"]
+        out[f"beta={beta}"] = res
+    print(json.dumps(out))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +237,8 @@ def main() -> int:
                     help="instead of the throughput step: the MLE comparisons (FP64 derivative-free vs "
                          "gradient-based and mixed precision) and single evaluations at n = 160,000")
     ap.add_argument("--big-n-side", type=int, default=400, help="grid side of the large single evaluations")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="instead of the throughput step: FP64 vs mixed-precision l on a 300 x 300 jittered grid")
     args = ap.parse_args()
 
     if args.copy_calibration:
@@ -209,6 +254,8 @@ def main() -> int:
 
     if args.mle_study:
         return mle_study(args)
+    if args.precision_study:
+        return precision_study(args)
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
