@@ -172,6 +172,33 @@ def simulate(x, y, theta, e) -> np.ndarray:
     return z
 
 
+def unpack_lower(Lp: np.ndarray, n: int) -> np.ndarray:
+    """Dense lower-triangular matrix from the packed row-major factor."""
+    L = np.zeros((n, n))
+    L[np.tril_indices(n)] = Lp
+    return L
+
+
+def predict(x, y, z, theta, xn, yn):
+    """Kriging at new locations (the conditional distribution of the Gaussian
+    field given the data, paper Section 4 and Section 5): with c_i the vector
+    of covariances between new point i and the observed points,
+        mean_i = c_i^T Sigma^-1 z,   mse_i = sigma^2 - c_i^T Sigma^-1 c_i,
+    evaluated through the oracle's own Cholesky factor L (Sigma = L L^T) as
+    (L^-1 c_i)^T (L^-1 z) and sigma^2 - |L^-1 c_i|^2; the triangular solves are
+    a library routine used as a step.  Returns (mean, mse)."""
+    import scipy.linalg
+
+    x, y, z, th, xn, yn = _f64(x), _f64(y), _f64(z), _f64(theta), _f64(xn), _f64(yn)
+    n, m = x.size, xn.size
+    L = unpack_lower(cholesky_packed(x, y, th), n)
+    S = matern_cov(np.concatenate([x, xn]), np.concatenate([y, yn]), th)
+    C = S[:n, n:]
+    v = scipy.linalg.solve_triangular(L, z, lower=True)
+    V = scipy.linalg.solve_triangular(L, C, lower=True)
+    return V.T @ v, th[0] - np.sum(V * V, axis=0)
+
+
 def dense_factor_lapack(x, y, theta) -> np.ndarray:
     """Lower Cholesky factor of the oracle's own dense Sigma(theta) (eq. 3) by
     LAPACK (numpy): the plain definition with a library factorisation as a

@@ -390,3 +390,56 @@ def test_lapack_factor_path_matches_unblocked_oracle(orc):
     z = inputgen.normals(x.size, seed=3)
     L = orc.dense_factor_lapack(x, y, th)
     assert orc.loglik_from_factor(L, z) == pytest.approx(orc.loglik(x, y, z, th), rel=1e-12)
+
+
+# ------------------------------------------------------------- kriging pins
+def test_predict_interpolates_the_data(orc):
+    # the conditional expectation at an observed location is the observation,
+    # with zero variance
+    import inputgen
+
+    x, y = inputgen.uniform(120, seed=40)
+    th = [1.7, 0.2, 1.3]
+    z = orc.simulate(x, y, th, inputgen.normals(120, seed=40))
+    idx = np.array([0, 7, 55, 119])
+    mean, mse = orc.predict(x, y, z, th, x[idx], y[idx])
+    np.testing.assert_allclose(mean, z[idx], rtol=1e-9, atol=1e-9)
+    assert np.all(np.abs(mse) <= 1e-8 * th[0])
+
+
+def test_predict_far_away_reverts_to_the_prior(orc):
+    import inputgen
+
+    x, y = inputgen.uniform(80, seed=41)
+    th = [2.5, 0.05, 0.8]
+    z = orc.simulate(x, y, th, inputgen.normals(80, seed=41))
+    mean, mse = orc.predict(x, y, z, th, np.array([60.0]), np.array([-40.0]))
+    assert abs(mean[0]) < 1e-300 and mse[0] == pytest.approx(th[0], rel=1e-15)
+
+
+def test_predict_markov_closed_form(orc):
+    # nu = 1/2 on a line: the exponential covariance is Markov, so kriging
+    # uses only the two neighbours of the new point (one beyond the ends):
+    #   w_a = r_a (1 - r_b^2) / (1 - r_a^2 r_b^2),  w_b = r_b (1 - r_a^2) / (1 - r_a^2 r_b^2),
+    #   mse = s2 (1 - w_a r_a - w_b r_b),  r = exp(-distance / beta)
+    rng = np.random.default_rng(42)
+    s = np.sort(rng.uniform(0.0, 3.0, 60))
+    x, y = s, np.zeros_like(s)
+    th = [1.4, 0.35, 0.5]
+    z = orc.simulate(x, y, th, rng.standard_normal(60))
+    q = np.array([-0.4, 0.71, 1.505, 2.2, 3.3])
+    mean, mse = orc.predict(x, y, z, th, q, np.zeros_like(q))
+    for k, p in enumerate(q):
+        if p < s[0] or p > s[-1]:
+            j = 0 if p < s[0] else len(s) - 1
+            r = np.exp(-abs(p - s[j]) / th[1])
+            em, ev = r * z[j], th[0] * (1.0 - r * r)
+        else:
+            b = np.searchsorted(s, p)
+            a = b - 1
+            ra, rb = np.exp(-(p - s[a]) / th[1]), np.exp(-(s[b] - p) / th[1])
+            d = 1.0 - ra * ra * rb * rb
+            wa, wb = ra * (1.0 - rb * rb) / d, rb * (1.0 - ra * ra) / d
+            em, ev = wa * z[a] + wb * z[b], th[0] * (1.0 - wa * ra - wb * rb)
+        assert mean[k] == pytest.approx(em, rel=1e-10, abs=1e-12)
+        assert mse[k] == pytest.approx(ev, rel=1e-9, abs=1e-12)
