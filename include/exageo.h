@@ -143,6 +143,21 @@ exageo_status exageo_loglik_grad(exageo_ctx *ctx, int64_t n, const double *x, co
                                  const double *z, const double theta[3], int precision, double *loglik,
                                  double grad[3], int64_t *info);
 
+/* Kriging (paper Sections 4 and 5, exact_predict): the conditional
+ * distribution of the field at m new locations given the n observations, in
+ * FP64,
+ *   mean[i] = c_i^T Sigma^-1 z,  mse[i] = sigma^2 - c_i^T Sigma^-1 c_i,
+ * c_i the covariances between new point i and the observed points.  x, y, z
+ * (n) and xnew, ynew, mean, mse (m) are DEVICE pointers in the caller's order;
+ * mse may be NULL (mean only: one fused pass over the n m pairs); with mse the
+ * library solves L V = C for blocks of up to 512 new points on MFMA, using a
+ * buffer of 2 * npad * 512 doubles it allocates itself (ENOMEM if it cannot).
+ * Statuses as for exageo_loglik (ENOTPD with *info when Sigma is not positive
+ * definite). */
+exageo_status exageo_predict(exageo_ctx *ctx, int64_t n, const double *x, const double *y, const double *z,
+                             const double theta[3], int64_t m, const double *xnew, const double *ynew,
+                             double *mean, double *mse, int64_t *info);
+
 /* Maximum-likelihood estimate within lb <= theta <= ub (host arrays of 3).
  * theta0 = NULL starts the derivative-free method at lb, as the paper's
  * optimisation list does, and the gradient method at sqrt(lb * ub).

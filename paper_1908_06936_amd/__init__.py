@@ -222,6 +222,29 @@ class Context:
         self._check(st, "loglik_grad", info.value)
         return ll.value, [g[0], g[1], g[2]]
 
+    def predict(self, x, y, z, theta, xnew, ynew, with_mse: bool = True):
+        """Kriging at (xnew, ynew): (mean, mse) float64 tensors (mse None
+        when with_mse is False)."""
+        x = _dev_f64(x, "x")
+        n = x.numel()
+        y, z = _dev_f64(y, "y", n), _dev_f64(z, "z", n)
+        xnew = _dev_f64(xnew, "xnew")
+        m = xnew.numel()
+        ynew = _dev_f64(ynew, "ynew", m)
+        mean = torch.empty(m, dtype=torch.float64, device=x.device)
+        mse = torch.empty(m, dtype=torch.float64, device=x.device) if with_mse else None
+        self._sync_stream()
+        self._ensure_ws(n, FP64, False)
+        info = ctypes.c_int64(0)
+        st = self._lib.exageo_predict(self._h, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                      ctypes.c_void_p(z.data_ptr()), _lib.darr(theta), m,
+                                      ctypes.c_void_p(xnew.data_ptr()), ctypes.c_void_p(ynew.data_ptr()),
+                                      ctypes.c_void_p(mean.data_ptr()),
+                                      ctypes.c_void_p(mse.data_ptr()) if mse is not None else None,
+                                      ctypes.byref(info))
+        self._check(st, "predict", info.value)
+        return mean, mse
+
     def mle(self, x, y, z, lb, ub, theta0=None, tol: float = 1e-4, max_iters: int = 0, method="dfo",
             precision="fp64"):
         """Bounded MLE; returns (theta_hat, loglik_hat, stats dict).  Raises on

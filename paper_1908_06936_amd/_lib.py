@@ -29,7 +29,7 @@ EXPORTS = [
     "exageo_create", "exageo_destroy", "exageo_set_stream", "exageo_workspace_bytes", "exageo_set_workspace",
     "exageo_set_mixed_policy", "exageo_set_mixed_fp64_band", "exageo_last_error", "exageo_matern_cov",
     "exageo_simulate", "exageo_loglik",
-    "exageo_loglik_grad", "exageo_mle", "exageo_get_timings", "exageo_set_profiling",
+    "exageo_loglik_grad", "exageo_mle", "exageo_predict", "exageo_get_timings", "exageo_set_profiling",
 ]
 
 _lib = None
@@ -70,6 +70,8 @@ def load():
     lib.exageo_loglik.argtypes = [p, i64, p, p, p, pd, i32, pd, pi64]
     lib.exageo_loglik_grad.restype = st
     lib.exageo_loglik_grad.argtypes = [p, i64, p, p, p, pd, i32, pd, pd, pi64]
+    lib.exageo_predict.restype = st
+    lib.exageo_predict.argtypes = [p, i64, p, p, p, pd, i64, p, p, p, p, pi64]
     lib.exageo_mle.restype = st
     lib.exageo_mle.argtypes = [p, i64, p, p, p, pd, pd, pd, d, i32, i32, i32, pd, pd, ctypes.POINTER(MleStats)]
     lib.exageo_get_timings.restype = ctypes.c_int

@@ -124,6 +124,9 @@ struct exageo_ctx {
   int32_t* hband = nullptr;  // pinned: pidx (noff) then li, lj (pool_cap each)
   size_t hband_words = 0;
   std::vector<int64_t> bfirst;
+  // kriging variance: library-owned right-hand-side blocks (C and V = L^-1 C)
+  double* pred_buf = nullptr;
+  size_t pred_bytes = 0;
   // side stream (default priority) for the lookahead panel, and its events
   hipStream_t side = nullptr;
   hipEvent_t ev_col = nullptr, ev_panel = nullptr;
@@ -561,6 +564,7 @@ void exageo_destroy(exageo_ctx* c) {
   if (c->hres) (void)hipHostFree(c->hres);
   if (c->htag) (void)hipHostFree(c->htag);
   if (c->hband) (void)hipHostFree(c->hband);
+  if (c->pred_buf) (void)hipFree(c->pred_buf);
   for (int i = 0; i < c->nev_created; ++i) (void)hipEventDestroy(c->ev[i]);
   if (c->side) {
     (void)hipStreamSynchronize(c->side);
@@ -819,3 +823,65 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
 }
 
 }  // extern "C"
+
+exageo_status exageo_predict(exageo_ctx* c, int64_t n, const double* x, const double* y, const double* z,
+                             const double theta[3], int64_t m, const double* xnew, const double* ynew, double* mean,
+                             double* mse, int64_t* info) {
+  if (!c) return EXAGEO_EINVAL;
+  c->err.clear();
+  if (info) *info = 0;
+  if (n < 1 || !x || !y || !z || !theta_ok(theta) || m < 0 || (m > 0 && (!xnew || !ynew || !mean)))
+    return fail(c, EXAGEO_EINVAL, "predict: invalid argument");
+  if (n > (int64_t)INT32_MAX || m > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n or m too large");
+  if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
+  Plan p = make_plan(n, c->ts, 0, EXAGEO_FP64);
+  exageo_status st = ensure_ws(c, p);
+  if (st) return st;
+  c->plan = p;
+  std::memset(c->timings, 0, sizeof c->timings);
+  rec(c, 0);
+  st = prepare_locations(c, p, x, y, z);
+  if (st) return st;
+  rec(c, 1);
+  double ll = 0.0;
+  st = eval_sorted(c, p, theta, false, &ll, nullptr, info, true);
+  if (st) return st;
+  if (m == 0) return EXAGEO_OK;
+  const exg::TileMat M = tilemat(c, p);
+  double* Xd = at<double>(c, p.off_xd);
+  double* av = at<double>(c, p.off_alpha);
+  // a = Sigma^-1 z = L^-T y, then the mean in one pass over (new, observed) pairs
+  exg::launch_copy(at<double>(c, p.off_av), at<double>(c, p.off_y), p.npad, c->stream);
+  exg::launch_trsv_bwd(M, Xd, at<double>(c, p.off_av), av, c->stream);
+  exg::launch_krige_mean(at<double>(c, p.off_xs), at<double>(c, p.off_ys), av, p.n, xnew, ynew, m,
+                         at<double>(c, p.off_qt), at<double>(c, p.off_cst), mean, c->stream);
+  if (mse) {
+    // blocks of up to 512 new points: C = Sigma(obs, new), V = L^-1 C
+    const int64_t mcap = std::min<int64_t>(512, (m + 127) / 128 * 128);
+    const size_t need = 2 * (size_t)p.npad * (size_t)mcap * 8;
+    if (c->pred_bytes < need) {
+      if (c->pred_buf) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipFree(c->pred_buf));
+        c->pred_buf = nullptr;
+        c->pred_bytes = 0;
+      }
+      hipError_t e = hipMalloc((void**)&c->pred_buf, need);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, EXAGEO_ENOMEM, "predict: hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
+      }
+      c->pred_bytes = need;
+    }
+    double* Cb = c->pred_buf;
+    double* Vb = c->pred_buf + (size_t)p.npad * mcap;
+    for (int64_t c0 = 0; c0 < m; c0 += mcap) {
+      const int64_t cols = std::min<int64_t>(mcap, (m - c0 + 127) / 128 * 128);
+      exg::launch_krige_mse(M, Xd, at<double>(c, p.off_xs), at<double>(c, p.off_ys), p.n, xnew, ynew, m, c0, cols,
+                            at<double>(c, p.off_qt), at<double>(c, p.off_cst), Cb, Vb, mse, c->stream);
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EXAGEO_OK;
+}

@@ -78,4 +78,12 @@ int64_t lauum_blocks(int64_t ts, int64_t NT);
 void launch_lauum_contract(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* av,
                            const double* qt, const double* cst, double* part, hipStream_t s);
 
+// k_predict.hip
+void launch_krige_mean(const double* xs, const double* ys, const double* av, int64_t nreal, const double* xn,
+                       const double* yn, int64_t m, const double* qt, const double* cst, double* mean, hipStream_t s);
+// variance of new points c0 .. c0 + ncols - 1 (ncols a multiple of 128; C, V: npad x ncols, ld npad)
+void launch_krige_mse(const TileMat& M, const double* Xd, const double* xs, const double* ys, int64_t nreal,
+                      const double* xn, const double* yn, int64_t m, int64_t c0, int64_t ncols, const double* qt,
+                      const double* cst, double* C, double* V, double* mse, hipStream_t s);
+
 }  // namespace exg
