@@ -199,6 +199,68 @@ def predict(x, y, z, theta, xn, yn):
     return V.T @ v, th[0] - np.sum(V * V, axis=0)
 
 
+def morton_order(x, y) -> np.ndarray:
+    """Z-order of the locations: coordinates scaled to [0, 65536) over their
+    bounding box, truncated to 16 bits, bits interleaved (x in the even bits),
+    ties by index.  This is the ordering whose consecutive runs of ts points
+    form the tiles of the diagonal-super-tile (DST) variant."""
+    x, y = _f64(x), _f64(y)
+    wx, wy = x.max() - x.min(), y.max() - y.min()
+    sx = 65535.999 / wx if wx > 0 else 0.0
+    sy = 65535.999 / wy if wy > 0 else 0.0
+    qx = ((x - x.min()) * sx).astype(np.uint64)
+    qy = ((y - y.min()) * sy).astype(np.uint64)
+    code = np.zeros(x.size, dtype=np.uint64)
+    for b in range(16):
+        code |= ((qx >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b)
+        code |= ((qy >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b + 1)
+    return np.lexsort((np.arange(x.size), code))
+
+
+def dst_covariance(x, y, theta, ts: int, band: int):
+    """The DST approximation (paper Section 2.1, Fig. 1(b)): Sigma(theta) of
+    the locations in Z-order, cut into tiles of ts points, with every tile
+    (I, J), |I - J| >= band, set to zero.  Returns (Sigma_DST, order)."""
+    order = morton_order(x, y)
+    xs, ys = _f64(x)[order], _f64(y)[order]
+    S = matern_cov(xs, ys, theta)
+    t = np.arange(xs.size) // ts
+    S[np.abs(t[:, None] - t[None, :]) >= band] = 0.0
+    return S, order
+
+
+def loglik_dst(x, y, z, theta, ts: int, band: int) -> float:
+    """eq. (2) with Sigma replaced by its DST approximation; the factorisation
+    is a library routine used as a step."""
+    S, order = dst_covariance(x, y, theta, ts, band)
+    return loglik_from_factor(np.linalg.cholesky(S), _f64(z)[order])
+
+
+def loglik_grad_dst(x, y, z, theta, ts: int, band: int):
+    """(l, grad l) of the DST likelihood: g_k = a^T dS_k a / 2 - tr(S^-1 dS_k) / 2
+    with S the DST covariance, dS_k its derivative (the derivative of eq. (3)
+    on the kept tiles, zero elsewhere) and a = S^-1 z."""
+    S, order = dst_covariance(x, y, theta, ts, band)
+    xs, ys, zs = _f64(x)[order], _f64(y)[order], _f64(z)[order]
+    n = xs.size
+    L = np.linalg.cholesky(S)
+    ll = loglik_from_factor(L, zs)
+    Si = np.linalg.inv(S)
+    a = Si @ zs
+    t = np.arange(n) // ts
+    dS = np.zeros((3, n, n))
+    for i in range(n):
+        for j in range(i + 1):
+            if abs(t[i] - t[j]) >= band:
+                continue
+            r = float(np.hypot(xs[i] - xs[j], ys[i] - ys[j]))
+            g = matern_grad(r, theta)
+            dS[:, i, j] = g
+            dS[:, j, i] = g
+    grad = np.array([0.5 * a @ dS[k] @ a - 0.5 * np.sum(Si * dS[k]) for k in range(3)])
+    return ll, grad
+
+
 def dense_factor_lapack(x, y, theta) -> np.ndarray:
     """Lower Cholesky factor of the oracle's own dense Sigma(theta) (eq. 3) by
     LAPACK (numpy): the plain definition with a library factorisation as a

@@ -443,3 +443,52 @@ def test_predict_markov_closed_form(orc):
             em, ev = wa * z[a] + wb * z[b], th[0] * (1.0 - wa * ra - wb * rb)
         assert mean[k] == pytest.approx(em, rel=1e-10, abs=1e-12)
         assert mse[k] == pytest.approx(ev, rel=1e-9, abs=1e-12)
+
+
+# --------------------------------------------------------------- DST pins
+def test_dst_band_covering_all_tiles_is_exact(orc):
+    import inputgen
+
+    x, y = inputgen.uniform(300, seed=70)
+    th = [1.1, 0.15, 0.9]
+    z = orc.simulate(x, y, th, inputgen.normals(300, seed=70))
+    assert orc.loglik_dst(x, y, z, th, 64, 5) == pytest.approx(orc.loglik(x, y, z, th), rel=1e-12)
+
+
+def test_dst_single_band_is_block_diagonal(orc):
+    # band 1 keeps only the diagonal tiles: l is the sum of the exact
+    # likelihoods of the tiles' point sets
+    import inputgen
+
+    x, y = inputgen.uniform(300, seed=71)
+    th = [0.9, 0.2, 1.4]
+    z = orc.simulate(x, y, th, inputgen.normals(300, seed=71))
+    order = orc.morton_order(x, y)
+    ref = sum(orc.loglik(x[order[s:s + 64]], y[order[s:s + 64]], z[order[s:s + 64]], th) for s in range(0, 300, 64))
+    assert orc.loglik_dst(x, y, z, th, 64, 1) == pytest.approx(ref, rel=1e-12)
+
+
+def test_morton_order_is_a_z_curve(orc):
+    # the four quadrants of the unit square come in Z order (lower-left,
+    # lower-right, upper-left, upper-right), recursively
+    x = np.array([0.1, 0.9, 0.1, 0.9, 0.2, 0.3])
+    y = np.array([0.1, 0.1, 0.9, 0.9, 0.05, 0.2])
+    order = orc.morton_order(x, y)
+    assert list(order[-3:]) == [1, 2, 3]
+    assert set(order[:3]) == {0, 4, 5}
+
+
+def test_dst_gradient_matches_differences(orc):
+    import inputgen
+
+    x, y = inputgen.uniform(90, seed=72)
+    th = np.array([1.2, 0.04, 0.8])
+    z = orc.simulate(x, y, th, inputgen.normals(90, seed=72))
+    _, g = orc.loglik_grad_dst(x, y, z, th, 32, 2)
+    for k in range(3):
+        h = 1e-6 * th[k]
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (orc.loglik_dst(x, y, z, tp, 32, 2) - orc.loglik_dst(x, y, z, tm, 32, 2)) / (2 * h)
+        assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-6)
