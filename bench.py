@@ -439,6 +439,31 @@ def main() -> int:
         print(f"[bench] jittered grid {key} done", file=sys.stderr, flush=True)
     ctx.set_mixed_policy(3.0)
     result["fp64_vs_mixed_jittered_grid_200x200"] = grid
+
+    # DST approximation (tiles |I - J| >= band set to zero) on the same grid,
+    # theta = (1, 0.03, 0.5): l alone, rate and difference from the exact l
+    th_d = [1.0, 0.03, 0.5]
+    Zd = ctx.simulate(Xg, Yg, th_d, E)
+    dst = {}
+    for band in (0, 8, 4, 2):
+        ctx.set_dst_band(band)
+        st, v, info = ctx.loglik_status(Xg, Yg, Zd, th_d)
+        if st != 0:
+            dst[f"band={band}"] = {"status": exa.STATUS_NAMES.get(st, st)}
+            continue
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            v = ctx.loglik(Xg, Yg, Zd, th_d)
+        torch.cuda.synchronize()
+        dst[f"band={band}"] = {"status": "OK", "loglik_evals_per_s": args.steps / (time.perf_counter() - t1),
+                               "loglik": v}
+    ctx.set_dst_band(0)
+    for d in dst.values():
+        if "loglik" in d:
+            d["rel_dl_vs_exact"] = abs(d["loglik"] - dst["band=0"]["loglik"]) / abs(dst["band=0"]["loglik"])
+    result["dst_jittered_grid_200x200_beta0.03"] = dst
+    print("[bench] DST done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(n, theta, args.cpu_sample)
     print(json.dumps(result))

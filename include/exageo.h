@@ -111,6 +111,15 @@ exageo_status exageo_set_mixed_policy(exageo_ctx *ctx, double band_factor);
  * BF16.  EINVAL if < 0. */
 exageo_status exageo_set_mixed_fp64_band(exageo_ctx *ctx, double fp64_band_factor);
 
+/* Diagonal-super-tile (DST) approximation (paper Section 2.1, Fig. 1(b)) of
+ * the likelihood calls (loglik, loglik_grad, mle; FP64 only): with the
+ * locations in the library's Z-order cut into tiles of ts points, every tile
+ * (I, J) with |I - J| >= band is set to zero, the factorisation then touches
+ * only the band (no fill-in outside it), and the score is that of the
+ * approximated likelihood.  0 (default) = exact.  simulate and predict stay
+ * exact.  EINVAL if band < 0. */
+exageo_status exageo_set_dst_band(exageo_ctx *ctx, int64_t band);
+
 /* Text of the last error of this context ("" if none).  Valid until the next
  * call on the context. */
 const char *exageo_last_error(const exageo_ctx *ctx);

@@ -134,6 +134,11 @@ class Context:
         if fp64_band is not None:
             self._check(self._lib.exageo_set_mixed_fp64_band(self._h, float(fp64_band)), "set_mixed_fp64_band")
 
+    def set_dst_band(self, band: int):
+        """DST approximation of the likelihood calls: tiles |I - J| >= band
+        set to zero (0 = exact)."""
+        self._check(self._lib.exageo_set_dst_band(self._h, int(band)), "set_dst_band")
+
     def set_profiling(self, on: bool = True):
         self._check(self._lib.exageo_set_profiling(self._h, int(on)), "set_profiling")
 

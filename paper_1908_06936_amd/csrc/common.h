@@ -65,6 +65,9 @@ struct TileMat {
   // pidx[off_index(i, j)] is the pool slot of tile (i, j) (-1: not a band tile)
   double* pool = nullptr;
   const int32_t* pidx = nullptr;
+  // diagonal-super-tile approximation: tiles (i, j) with i - j >= dst are
+  // zero and stay zero (no fill-in outside a tile band); 0 = exact
+  int64_t dst = 0;
 };
 
 // precision tag of an off-diagonal tile in mixed precision

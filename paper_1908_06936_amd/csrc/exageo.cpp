@@ -31,6 +31,7 @@ struct Plan {
          off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_p32 = 0, off_pbt = 0, off_tag = 0,
          off_tbox = 0, off_pool = 0, off_pidx = 0, off_bli = 0, off_blj = 0;
   int64_t pool_cap = 0;  // mixed precision: FP64 band tiles the pool can hold
+  int64_t dst = 0;       // DST tile band (0: exact)
   size_t bytes = 0;
 };
 
@@ -104,6 +105,7 @@ struct exageo_ctx {
   hipStream_t stream = nullptr;
   double band_factor = 3.0;     // BF16 at or beyond band_factor * beta
   double fp64_band_factor = 0.0;  // FP64 below fp64_band_factor * beta
+  int64_t dst_band = 0;           // DST approximation of loglik / loglik_grad / mle (0: exact)
   bool profiling = false;
   std::string err;
   // workspace
@@ -321,6 +323,7 @@ exg::TileMat tilemat(exageo_ctx* c, const Plan& p) {
     M.pool = at<double>(c, p.off_pool);
     M.pidx = at<int32_t>(c, p.off_pidx);
   }
+  M.dst = p.dst;
   return M;
 }
 
@@ -375,7 +378,9 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
         below = below_fp64(M, k);
       }
     }
-    exg::launch_panel(M.diag + k * tt, below, p.ts, p.NT, k, p.n, at<double>(c, p.off_dinv) + k * p.T * BLKH * BLKH,
+    // DST: the rows below the band are zero and are left alone
+    const int64_t prow = p.dst > 0 ? std::min<int64_t>(p.n, (k + p.dst) * p.ts) : p.n;
+    exg::launch_panel(M.diag + k * tt, below, p.ts, p.NT, k, prow, at<double>(c, p.off_dinv) + k * p.T * BLKH * BLKH,
                       at<double>(c, p.off_ld) + k * p.T, at<unsigned long long>(c, p.off_info), s);
     if (p.mixed && k + 1 < p.NT) {
       exg::launch_panel_scatter(M, k, tag, below, at<float>(c, p.off_p32) + (k & 1) * phalf, s);
@@ -408,13 +413,17 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
     if (slot + 1 < c->nev_created) rec(c, slot + 1);
     HIPCHK(c, hipStreamWaitEvent(S, c->ev_panel, 0));
     below = next;
-    nupd += p.NT - k - 1 >= 2 ? 2 : 1;  // launches of k_chol_update in this step
+    {
+      const int64_t mt = p.dst > 0 ? std::min<int64_t>(p.NT - k - 1, p.dst - 1) : p.NT - k - 1;
+      nupd += mt >= 2 ? 2 : (mt == 1 ? 1 : 0);  // launches of k_chol_update in this step
+    }
     // algorithmic flops of this update over the real rows, by target precision
-    for (int64_t j = k + 1; j < p.NT; ++j) {
+    const int64_t iend = p.dst > 0 ? std::min<int64_t>(p.NT, k + p.dst) : p.NT;  // DST: rows in the band
+    for (int64_t j = k + 1; j < iend; ++j) {
       const double rj = (double)std::min<int64_t>(p.ts, p.n - j * p.ts);
       upd_flops += rj * (rj + 1.0) * (double)p.ts;  // SYRK
       flops_by[2] += rj * (rj + 1.0) * (double)p.ts;
-      for (int64_t i = j + 1; i < p.NT; ++i) {
+      for (int64_t i = j + 1; i < iend; ++i) {
         const double ri = (double)std::min<int64_t>(p.ts, p.n - i * p.ts);
         const double f = 2.0 * ri * rj * (double)p.ts;
         upd_flops += f;
@@ -599,6 +608,12 @@ exageo_status exageo_set_workspace(exageo_ctx* c, void* dev_ptr, size_t bytes) {
   return EXAGEO_OK;
 }
 
+exageo_status exageo_set_dst_band(exageo_ctx* c, int64_t band) {
+  if (!c || band < 0) return EXAGEO_EINVAL;
+  c->dst_band = band;
+  return EXAGEO_OK;
+}
+
 exageo_status exageo_set_mixed_fp64_band(exageo_ctx* c, double fp64_band_factor) {
   if (!c || !(fp64_band_factor >= 0.0) || !std::isfinite(fp64_band_factor)) return EXAGEO_EINVAL;
   c->fp64_band_factor = fp64_band_factor;
@@ -702,7 +717,10 @@ static exageo_status loglik_common(exageo_ctx* c, int64_t n, const double* x, co
   if (precision != EXAGEO_FP64 && precision != EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "unknown precision");
   if (n > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n too large");
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
+  if (precision == EXAGEO_MIXED && c->dst_band > 0)
+    return fail(c, EXAGEO_EINVAL, "the DST approximation runs in FP64 only");
   Plan p = make_plan(n, c->ts, want_grad, precision);
+  p.dst = c->dst_band;
   exageo_status st = ensure_ws(c, p);
   if (st) return st;
   c->plan = p;
@@ -773,7 +791,10 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
   }
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
   const bool want_grad = method == EXAGEO_LBFGSB;
+  if (precision == EXAGEO_MIXED && c->dst_band > 0)
+    return fail(c, EXAGEO_EINVAL, "the DST approximation runs in FP64 only");
   Plan p = make_plan(n, c->ts, want_grad, precision);
+  p.dst = c->dst_band;
   exageo_status st = ensure_ws(c, p);
   if (st) return st;
   c->plan = p;

@@ -242,7 +242,8 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract(TileMat M, int T, int
   const int u = sub / T, v = sub % T;
   int64_t I, J;
   tri_decode(p, &I, &J);
-  if ((I == J && u < v) || I * ts + u * BLK >= nreal || J * ts + v * BLK >= nreal) {
+  // DST: dSigma is zero outside the tile band, so are those blocks' terms
+  if ((I == J && u < v) || I * ts + u * BLK >= nreal || J * ts + v * BLK >= nreal || (M.dst > 0 && I - J >= M.dst)) {
     if (threadIdx.x < 3) part[3 * b + threadIdx.x] = 0.0;
     return;
   }
@@ -271,7 +272,8 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract(TileMat M, int T, int
 void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_t nreal, bool diag_only, int part,
                         hipStream_t s) {
   const int T = (int)(M.ts / BLK);
-  const int64_t m = M.NT - k - 1;  // trailing tiles
+  int64_t m = M.NT - k - 1;  // trailing tiles
+  if (M.dst > 0 && m > M.dst - 1) m = M.dst - 1;  // DST: L_ik = 0 for i - k >= dst
   if (m <= 0) return;
   int mode;
   int64_t off, npairs;

@@ -125,10 +125,13 @@ __global__ __launch_bounds__(256) void k_gen_tiles(TileMat M, int T, int64_t nre
   } else {
     out16 = (uint16_t*)((float*)M.off + off_index(I, J, M.NT) * ts * ts) + o;
   }
+  const bool zero_tile = M.dst > 0 && I - J >= M.dst;  // outside the DST band
   for (int c = c0; c < BLK; c += 2) {
     const int64_t gj = J * ts + v * BLK + c;
     double val;
-    if (ipad || gj >= nreal) {
+    if (zero_tile) {
+      val = 0.0;
+    } else if (ipad || gj >= nreal) {
       val = (gi == gj) ? 1.0 : 0.0;
     } else {
       const double dx = xi - xs[gj], dy = yi - ys[gj];
