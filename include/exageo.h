@@ -111,6 +111,15 @@ exageo_status exageo_set_mixed_policy(exageo_ctx *ctx, double band_factor);
  * BF16.  EINVAL if < 0. */
 exageo_status exageo_set_mixed_fp64_band(exageo_ctx *ctx, double fp64_band_factor);
 
+/* Distance between locations (paper Section 3, the dmetric argument):
+ * EXAGEO_EUCLIDEAN (default) on (x, y), or EXAGEO_GREAT_CIRCLE: x = longitude
+ * and y = latitude in degrees, distance along the sphere of radius 6371 (km,
+ * so beta is in km) by the haversine formula.  Applies to every later call.
+ * With great-circle distances the mixed-precision distance rules (BF16 band,
+ * FP64 band) are not applied: every off-diagonal tile is FP32. */
+enum { EXAGEO_EUCLIDEAN = 0, EXAGEO_GREAT_CIRCLE = 1 };
+exageo_status exageo_set_distance(exageo_ctx *ctx, int metric);
+
 /* Diagonal-super-tile (DST) approximation (paper Section 2.1, Fig. 1(b)) of
  * the likelihood calls (loglik, loglik_grad, mle; FP64 only): with the
  * locations in the library's Z-order cut into tiles of ts points, every tile

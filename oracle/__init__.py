@@ -261,6 +261,52 @@ def loglik_grad_dst(x, y, z, theta, ts: int, band: int):
     return ll, grad
 
 
+EARTH_RADIUS_KM = 6371.0
+
+
+def great_circle(lon1, lat1, lon2, lat2):
+    """Great-circle distance in km on a sphere of radius 6371 between
+    (longitude, latitude) points in degrees (haversine, central angle by
+    atan2 as in Veness 2010)."""
+    p1, p2 = np.radians(lat1), np.radians(lat2)
+    dp, dl = p2 - p1, np.radians(np.asarray(lon2) - np.asarray(lon1))
+    a = np.sin(dp / 2) ** 2 + np.cos(p1) * np.cos(p2) * np.sin(dl / 2) ** 2
+    a = np.clip(a, 0.0, 1.0)
+    return EARTH_RADIUS_KM * 2.0 * np.arctan2(np.sqrt(a), np.sqrt(1.0 - a))
+
+
+def matern_cov_gc(lon, lat, theta) -> np.ndarray:
+    """eq. (3) with great-circle distances (the dmetric option, Section 3)."""
+    lon, lat = _f64(lon), _f64(lat)
+    n = lon.size
+    D = great_circle(lon[:, None], lat[:, None], lon[None, :], lat[None, :])
+    S = np.empty((n, n))
+    for i in range(n):
+        for j in range(i + 1):
+            S[i, j] = S[j, i] = matern(D[i, j], theta)
+    return S
+
+
+def loglik_grad_gc(lon, lat, z, theta):
+    """(l, grad l) with great-circle distances; dense factorisation and inverse
+    by library routines."""
+    lon, lat, z = _f64(lon), _f64(lat), _f64(z)
+    n = lon.size
+    S = matern_cov_gc(lon, lat, theta)
+    ll = loglik_from_factor(np.linalg.cholesky(S), z)
+    Si = np.linalg.inv(S)
+    a = Si @ z
+    D = great_circle(lon[:, None], lat[:, None], lon[None, :], lat[None, :])
+    dS = np.zeros((3, n, n))
+    for i in range(n):
+        for j in range(i + 1):
+            g = matern_grad(D[i, j], theta)
+            dS[:, i, j] = g
+            dS[:, j, i] = g
+    grad = np.array([0.5 * a @ dS[k] @ a - 0.5 * np.sum(Si * dS[k]) for k in range(3)])
+    return ll, grad
+
+
 def dense_factor_lapack(x, y, theta) -> np.ndarray:
     """Lower Cholesky factor of the oracle's own dense Sigma(theta) (eq. 3) by
     LAPACK (numpy): the plain definition with a library factorisation as a

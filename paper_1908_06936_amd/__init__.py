@@ -134,6 +134,12 @@ class Context:
         if fp64_band is not None:
             self._check(self._lib.exageo_set_mixed_fp64_band(self._h, float(fp64_band)), "set_mixed_fp64_band")
 
+    def set_distance(self, metric: str):
+        """'euclidean' (default) or 'great_circle' (x = longitude, y = latitude
+        in degrees, km on a sphere of radius 6371)."""
+        m = {"euclidean": _lib.EUCLIDEAN, "great_circle": _lib.GREAT_CIRCLE}[metric]
+        self._check(self._lib.exageo_set_distance(self._h, m), "set_distance")
+
     def set_dst_band(self, band: int):
         """DST approximation of the likelihood calls: tiles |I - J| >= band
         set to zero (0 = exact)."""

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libexageo.so")
 
 OK, EINVAL, ENOTPD, ENOMEM, EDEVICE, ENOCONV = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
+EUCLIDEAN, GREAT_CIRCLE = 0, 1
 DFO, LBFGSB = 0, 1
 
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOTPD: "ENOTPD", ENOMEM: "ENOMEM",
@@ -27,7 +28,7 @@ class MleStats(ctypes.Structure):
 
 EXPORTS = [
     "exageo_create", "exageo_destroy", "exageo_set_stream", "exageo_workspace_bytes", "exageo_set_workspace",
-    "exageo_set_mixed_policy", "exageo_set_mixed_fp64_band", "exageo_set_dst_band", "exageo_last_error",
+    "exageo_set_mixed_policy", "exageo_set_mixed_fp64_band", "exageo_set_dst_band", "exageo_set_distance", "exageo_last_error",
     "exageo_matern_cov",
     "exageo_simulate", "exageo_loglik",
     "exageo_loglik_grad", "exageo_mle", "exageo_predict", "exageo_get_timings", "exageo_set_profiling",
@@ -63,6 +64,8 @@ def load():
     lib.exageo_set_mixed_fp64_band.argtypes = [p, d]
     lib.exageo_set_dst_band.restype = st
     lib.exageo_set_dst_band.argtypes = [p, i64]
+    lib.exageo_set_distance.restype = st
+    lib.exageo_set_distance.argtypes = [p, i32]
     lib.exageo_last_error.restype = ctypes.c_char_p
     lib.exageo_last_error.argtypes = [p]
     lib.exageo_matern_cov.restype = st

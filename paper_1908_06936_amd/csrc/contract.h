@@ -19,9 +19,8 @@ __device__ __forceinline__ void contract_entry(int64_t gi, int64_t gj, double xi
                                                const double* __restrict__ cst, double (&g3)[3]) {
   const double wgt = (gi == gj) ? 0.5 : 1.0;  // (w / 2) with w = 1 or 2
   const double f = wgt * (ai * av[gj] - wv);
-  const double dx = xi - xs[gj], dy = yi - ys[gj];
   double d0, d1, d2;
-  matern_grad(sqrt(dx * dx + dy * dy), cst, qt, &d0, &d1, &d2);
+  matern_grad(loc_dist(xi, yi, xs[gj], ys[gj], cst), cst, qt, &d0, &d1, &d2);
   g3[0] += f * d0;
   g3[1] += f * d1;
   g3[2] += f * d2;

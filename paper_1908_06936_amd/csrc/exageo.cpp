@@ -106,6 +106,7 @@ struct exageo_ctx {
   double band_factor = 3.0;     // BF16 at or beyond band_factor * beta
   double fp64_band_factor = 0.0;  // FP64 below fp64_band_factor * beta
   int64_t dst_band = 0;           // DST approximation of loglik / loglik_grad / mle (0: exact)
+  int metric = EXAGEO_EUCLIDEAN;  // distance between locations
   bool profiling = false;
   std::string err;
   // workspace
@@ -250,6 +251,9 @@ exageo_status upload_tags(exageo_ctx* c, const Plan& p, double beta, double* fra
     c->hband_words = words;
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));  // previous upload consumed
+  // the tile boxes are planar in (x, y): with great-circle distances the
+  // distance rules are not applied and every off-diagonal tile is FP32
+  const bool planar = c->metric == EXAGEO_EUCLIDEAN;
   const double band16 = c->band_factor * beta, band64 = c->fp64_band_factor * beta;
   int32_t* pidx = c->hband;
   int32_t* li = c->hband + noff;
@@ -266,9 +270,9 @@ exageo_status upload_tags(exageo_ctx* c, const Plan& p, double beta, double* fra
       const double d = std::sqrt(dx * dx + dy * dy);
       const int64_t idx = exg::off_index(i, j, p.NT);
       pidx[idx] = -1;
-      const bool bf = c->band_factor > 0.0 && d >= band16;
+      const bool bf = planar && c->band_factor > 0.0 && d >= band16;
       c->htag[idx] = bf ? exg::TAG_BF16 : exg::TAG_F32;
-      if (!bf && d < band64) cand.emplace_back(d, idx);
+      if (planar && !bf && d < band64) cand.emplace_back(d, idx);
       ++ntot;
     }
   }
@@ -350,7 +354,7 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
     c->timings[12] = p.NT > 1 ? 1.0 - fbf - f64 : 0.0;
     c->timings[14] = f64;
   }
-  exg::launch_quad_table(theta, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
+  exg::launch_quad_table(theta, c->metric, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   exg::launch_fill_info(at<unsigned long long>(c, p.off_info), c->stream);
   exg::launch_gen_tiles(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), at<double>(c, p.off_qt),
                         at<double>(c, p.off_cst), tag, c->stream);
@@ -608,6 +612,12 @@ exageo_status exageo_set_workspace(exageo_ctx* c, void* dev_ptr, size_t bytes) {
   return EXAGEO_OK;
 }
 
+exageo_status exageo_set_distance(exageo_ctx* c, int metric) {
+  if (!c || (metric != EXAGEO_EUCLIDEAN && metric != EXAGEO_GREAT_CIRCLE)) return EXAGEO_EINVAL;
+  c->metric = metric;
+  return EXAGEO_OK;
+}
+
 exageo_status exageo_set_dst_band(exageo_ctx* c, int64_t band) {
   if (!c || band < 0) return EXAGEO_EINVAL;
   c->dst_band = band;
@@ -658,7 +668,7 @@ exageo_status exageo_matern_cov(exageo_ctx* c, int64_t n, const double* x, const
   Plan p = make_plan(1, c->ts, 0);
   exageo_status st = ensure_ws(c, p);
   if (st) return st;
-  exg::launch_quad_table(theta, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
+  exg::launch_quad_table(theta, c->metric, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   exg::launch_gen_dense(cov, ldc, n, x, y, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));

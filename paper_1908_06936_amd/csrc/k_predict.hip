@@ -25,8 +25,7 @@ __global__ __launch_bounds__(256) void k_krige_mean(const double* __restrict__ x
   const double px = xn[i], py = yn[i];
   double s = 0.0;
   for (int64_t j = threadIdx.x; j < nreal; j += 256) {
-    const double dx = px - xs[j], dy = py - ys[j];
-    s += matern_value(sqrt(dx * dx + dy * dy), cst, qt) * av[j];
+    s += matern_value(loc_dist(px, py, xs[j], ys[j], cst), cst, qt) * av[j];
   }
   double v[1] = {s};
   block_sum<1>(v, red);
@@ -46,8 +45,7 @@ __global__ __launch_bounds__(256) void k_gen_cross(const double* __restrict__ xs
   if (j >= npad || c >= ncols) return;
   double v = 0.0;
   if (j < nreal && c0 + c < m) {
-    const double dx = xs[j] - xn[c0 + c], dy = ys[j] - yn[c0 + c];
-    v = matern_value(sqrt(dx * dx + dy * dy), cst, qt);
+    v = matern_value(loc_dist(xs[j], ys[j], xn[c0 + c], yn[c0 + c], cst), cst, qt);
   }
   C[j + c * ldc] = v;
 }

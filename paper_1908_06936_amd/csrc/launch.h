@@ -12,7 +12,7 @@ namespace exg {
 // k_matern.hip
 // doubles of the per-theta table array (quadrature nodes + Chebyshev tables)
 int64_t quad_table_doubles();
-void launch_quad_table(const double theta[3], double* qt, double* cst, hipStream_t s);
+void launch_quad_table(const double theta[3], int metric, double* qt, double* cst, hipStream_t s);
 void launch_gen_tiles(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* qt,
                       const double* cst, const uint8_t* tag, hipStream_t s);
 void launch_gen_dense(double* cov, int64_t ldc, int64_t n, const double* x, const double* y, const double* qt,

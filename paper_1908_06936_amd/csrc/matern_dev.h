@@ -53,7 +53,23 @@ constexpr int QT_CHEB_OFF = QNB * QNK * QW;
 constexpr int QT_TOTAL = QT_CHEB_OFF + CH_NSEG * CH_STRIDE;
 
 // per-theta constants written by the table kernel
-enum { C_S2 = 0, C_BETA, C_NU, C_C, C_PSI, C_S2C, C_COUNT = 8 };
+enum { C_S2 = 0, C_BETA, C_NU, C_C, C_PSI, C_S2C, C_METRIC, C_COUNT = 8 };
+
+constexpr double EARTH_RADIUS_KM = 6371.0;
+
+// distance between two locations: Euclidean, or (cst[C_METRIC] = 1) the
+// great-circle distance in km between (longitude, latitude) pairs in degrees
+// by the haversine formula
+__device__ __forceinline__ double loc_dist(double x1, double y1, double x2, double y2, const double* __restrict__ cst) {
+  if (cst[C_METRIC] == 0.0) {
+    const double dx = x1 - x2, dy = y1 - y2;
+    return sqrt(dx * dx + dy * dy);
+  }
+  const double d2r = 3.14159265358979323846 / 180.0;
+  const double sp = sin(0.5 * (y2 - y1) * d2r), sl = sin(0.5 * (x2 - x1) * d2r);
+  const double a = sp * sp + cos(y1 * d2r) * cos(y2 * d2r) * sl * sl;
+  return 2.0 * EARTH_RADIUS_KM * asin(fmin(1.0, sqrt(a)));
+}
 
 __device__ __forceinline__ int quad_bucket(double x) {
   if (x <= 9.0) return 0;

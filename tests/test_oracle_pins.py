@@ -492,3 +492,41 @@ def test_dst_gradient_matches_differences(orc):
         tm[k] -= h
         fd = (orc.loglik_dst(x, y, z, tp, 32, 2) - orc.loglik_dst(x, y, z, tm, 32, 2)) / (2 * h)
         assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-6)
+
+
+# -------------------------------------------------- great-circle distance pins
+def test_great_circle_closed_forms(orc):
+    R = orc.EARTH_RADIUS_KM
+    assert orc.great_circle(0.0, 0.0, 90.0, 0.0) == pytest.approx(R * np.pi / 2, rel=1e-14)
+    assert orc.great_circle(10.0, 90.0, -70.0, -90.0) == pytest.approx(R * np.pi, rel=1e-14)
+    assert orc.great_circle(30.0, 0.0, 30.0, 45.0) == pytest.approx(R * np.pi / 4, rel=1e-14)
+    assert orc.great_circle(179.5, 0.0, -179.5, 0.0) == pytest.approx(R * np.radians(1.0), rel=1e-12)
+    assert orc.great_circle(12.0, -33.0, 12.0, -33.0) == 0.0
+
+
+def test_great_circle_small_patch_matches_planar(orc):
+    # on a patch of 1e-3 degrees at the equator the sphere is flat to ~1e-13:
+    # the likelihood equals the Euclidean one in km
+    import inputgen
+
+    u, v = inputgen.uniform(120, seed=80)
+    lon, lat = 1e-3 * u, 1e-3 * v
+    km = orc.EARTH_RADIUS_KM * np.radians(1.0)
+    th = [1.3, 0.02, 0.9]
+    z = orc.simulate(lon * km, lat * km, th, inputgen.normals(120, seed=80))
+    l_gc, _ = orc.loglik_grad_gc(lon, lat, z, th)
+    assert l_gc == pytest.approx(orc.loglik(lon * km, lat * km, z, th), rel=1e-9)
+
+
+def test_great_circle_likelihood_is_rotation_invariant(orc):
+    import inputgen
+
+    u, v = inputgen.uniform(60, seed=81)
+    lon, lat = 360.0 * u - 180.0, 160.0 * v - 80.0
+    th = [1.0, 3000.0, 0.7]
+    S = orc.matern_cov_gc(lon, lat, th)
+    z = np.linalg.cholesky(S) @ inputgen.normals(60, seed=81)
+    l0, g0 = orc.loglik_grad_gc(lon, lat, z, th)
+    l1, g1 = orc.loglik_grad_gc(lon + 77.0, lat, z, th)
+    assert l1 == pytest.approx(l0, rel=1e-12)
+    np.testing.assert_allclose(g1, g0, rtol=1e-9)
