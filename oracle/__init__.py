@@ -66,6 +66,8 @@ def _load():
     lib.oracle_matern_grad.argtypes = [d, p, p]
     lib.oracle_matern_cov.restype = ctypes.c_int
     lib.oracle_matern_cov.argtypes = [i64, p, p, p, p]
+    lib.oracle_matern_dcov.restype = ctypes.c_int
+    lib.oracle_matern_dcov.argtypes = [i64, p, p, p, ctypes.c_int, p]
     lib.oracle_cholesky.restype = ctypes.c_int
     lib.oracle_cholesky.argtypes = [i64, p, p, p, p, p]
     lib.oracle_simulate.restype = ctypes.c_int
@@ -146,6 +148,34 @@ def matern_cov(x, y, theta) -> np.ndarray:
     if st:
         raise OracleError(st)
     return cov
+
+
+def matern_dcov(x, y, theta, comp: int) -> np.ndarray:
+    """Dense matrix of dSigma/dtheta_comp (comp 0: sigma^2, 1: beta, 2: nu)."""
+    x, y, th = _f64(x), _f64(y), _f64(theta)
+    n = x.size
+    out = np.empty((n, n))
+    st = _load().oracle_matern_dcov(n, _ptr(x), _ptr(y), _ptr(th), int(comp), _ptr(out))
+    if st:
+        raise OracleError(st)
+    return out
+
+
+def fisher(x, y, theta) -> np.ndarray:
+    """Fisher information of theta = (sigma^2, beta, nu) for the zero-mean
+    Gaussian field observed at (x, y) (the exact_fisher function of the
+    package's API table, Section 3): the expected negative Hessian of eq. (2),
+        I_jk = tr(Sigma^-1 dSigma_j Sigma^-1 dSigma_k) / 2.
+    With A_j = Sigma^-1 dSigma_j (a library solve used as a step) the trace is
+    the sum of the elementwise product of A_j and A_k^T."""
+    x, y, th = _f64(x), _f64(y), _f64(theta)
+    S = matern_cov(x, y, th)
+    A = [np.linalg.solve(S, matern_dcov(x, y, th, k)) for k in range(3)]
+    I = np.empty((3, 3))
+    for j in range(3):
+        for k in range(3):
+            I[j, k] = 0.5 * np.sum(A[j] * A[k].T)
+    return I
 
 
 def cholesky_packed(x, y, theta) -> np.ndarray:

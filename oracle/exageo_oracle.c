@@ -375,6 +375,20 @@ int oracle_matern_cov(int64_t n, const double *x, const double *y, const double 
   return OR_OK;
 }
 
+/* Full n x n matrix of one theta-derivative of the covariance (comp 0: sigma2,
+ * 1: beta, 2: nu), row-major, out[i*n + j]. */
+int oracle_matern_dcov(int64_t n, const double *x, const double *y, const double *theta, int comp, double *out) {
+  if (n < 1 || comp < 0 || comp > 2 || !or_theta_ok(theta)) return OR_EINVAL;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double d[3];
+      oracle_matern_grad(or_dist(x, y, i, j), theta, d);
+      out[i * n + j] = d[comp];
+    }
+  return OR_OK;
+}
+
 /* packed lower, row-major: element (i, j), j <= i, at i (i + 1) / 2 + j */
 #define PK(i, j) ((size_t)(i) * ((size_t)(i) + 1) / 2 + (size_t)(j))
 

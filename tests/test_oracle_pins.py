@@ -530,3 +530,67 @@ def test_great_circle_likelihood_is_rotation_invariant(orc):
     l1, g1 = orc.loglik_grad_gc(lon + 77.0, lat, z, th)
     assert l1 == pytest.approx(l0, rel=1e-12)
     np.testing.assert_allclose(g1, g0, rtol=1e-9)
+
+
+# ------------------------------------------------------- Fisher information
+def test_fisher_variance_entry_and_symmetry(orc):
+    # dSigma/dsigma^2 = Sigma / sigma^2, so I_ss = n / (2 sigma^4) exactly and
+    # I_sk = tr(Sigma^-1 dSigma_k) / (2 sigma^2); the matrix is symmetric PD.
+    x, y = inputgen.uniform(150, seed=91)
+    th = np.array([1.7, 0.08, 1.3])
+    I = orc.fisher(x, y, th)
+    assert I[0, 0] == pytest.approx(150 / (2 * th[0] ** 2), rel=1e-10)
+    S = orc.matern_cov(x, y, th)
+    for k in (1, 2):
+        tr = np.trace(np.linalg.solve(S, orc.matern_dcov(x, y, th, k)))
+        assert I[0, k] == pytest.approx(tr / (2 * th[0]), rel=1e-9)
+    np.testing.assert_allclose(I, I.T, rtol=1e-9)
+    assert np.all(np.linalg.eigvalsh(I) > 0)
+
+
+def test_fisher_markov_closed_form(orc):
+    # nu = 1/2 on a line: z_1 ~ N(0, s2), z_i | z_{i-1} ~ N(rho_i z_{i-1}, v_i),
+    # rho_i = exp(-d_i / beta), v_i = s2 (1 - rho_i^2).  The information adds
+    # over the factors; a Gaussian factor N(m z', v) with E z'^2 = s2 carries
+    # s2 grad(m) grad(m)^T / v + grad(ln v) grad(ln v)^T / 2.
+    n, s2, beta = 300, 0.9, 0.07
+    t, y0 = inputgen.collinear(n, mean_gap=0.01, seed=5)
+    d = np.diff(np.sort(t))
+    rho = np.exp(-d / beta)
+    drho = np.stack([np.zeros_like(rho), rho * d / beta ** 2])
+    dlnv = np.stack([np.full_like(rho, 1.0 / s2), -2.0 * rho * drho[1] / (1.0 - rho ** 2)])
+    v = s2 * (1.0 - rho ** 2)
+    ref = np.zeros((2, 2))
+    ref[0, 0] = 0.5 / s2 ** 2
+    ref += s2 * (drho / v) @ drho.T + 0.5 * dlnv @ dlnv.T
+    I = orc.fisher(t, y0, [s2, beta, 0.5])
+    np.testing.assert_allclose(I[:2, :2], ref, rtol=1e-9)
+
+
+def test_fisher_is_the_hessian_of_the_expected_loglik(orc):
+    # I(theta0) = -Hessian of f(theta) = E_theta0[l(theta)]
+    #           = -(ln det Sigma(theta) + tr(Sigma(theta)^-1 Sigma(theta0))) / 2 + const,
+    # which needs only covariance values: central second differences pin every
+    # entry, the nu row included, independently of the derivative matrices.
+    x, y = inputgen.uniform(120, seed=17)
+    th0 = np.array([1.2, 0.09, 0.9])
+    S0 = orc.matern_cov(x, y, th0)
+
+    def f(th):
+        S = orc.matern_cov(x, y, th)
+        return -0.5 * (np.linalg.slogdet(S)[1] + np.trace(np.linalg.solve(S, S0)))
+
+    def hess(rel):
+        h = rel * th0
+        H = np.empty((3, 3))
+        for j in range(3):
+            for k in range(3):
+                ej, ek = np.eye(3)[j] * h[j], np.eye(3)[k] * h[k]
+                H[j, k] = (f(th0 + ej + ek) - f(th0 + ej - ek) - f(th0 - ej + ek)
+                           + f(th0 - ej - ek)) / (4 * h[j] * h[k])
+        return H
+
+    H = (4 * hess(1e-3) - hess(2e-3)) / 3  # Richardson: O(h^4)
+    I = orc.fisher(x, y, th0)
+    scale = np.sqrt(np.outer(np.diag(I), np.diag(I)))
+    assert np.max(np.abs(-H - I) / scale) < 1e-7
