@@ -176,6 +176,21 @@ exageo_status exageo_predict(exageo_ctx *ctx, int64_t n, const double *x, const 
                              const double theta[3], int64_t m, const double *xnew, const double *ynew,
                              double *mean, double *mse, int64_t *info);
 
+/* Fisher information of theta = (sigma2, beta, nu) at the n locations (the
+ * package's exact_fisher function, Section 3's table of functions): the
+ * expected negative Hessian of eq. (2),
+ *   I_jk = tr(Sigma^-1 dSigma_j Sigma^-1 dSigma_k) / 2,
+ * computed in FP64 whatever the context's precision settings, as
+ * I_jk = <B_j, B_k> / 2 with B_j = L^-1 dSigma_j L^-T (B_sigma2 = I / sigma2,
+ * B_beta and B_nu by FP64 MFMA products with the regenerated derivative
+ * matrices).  x, y are DEVICE pointers (n doubles, caller order); fisher is a
+ * HOST array of 9 doubles receiving I row-major.  The library allocates
+ * 3 npad^2 doubles of its own for the call (npad = n rounded up to the tile
+ * size) and frees them before returning (ENOMEM if it cannot).  EINVAL while
+ * the DST approximation is on; ENOTPD with *info as for exageo_loglik. */
+exageo_status exageo_fisher(exageo_ctx *ctx, int64_t n, const double *x, const double *y, const double theta[3],
+                            double fisher[9], int64_t *info);
+
 /* Maximum-likelihood estimate within lb <= theta <= ub (host arrays of 3).
  * theta0 = NULL starts the derivative-free method at lb, as the paper's
  * optimisation list does, and the gradient method at sqrt(lb * ub).

@@ -16,6 +16,8 @@ from __future__ import annotations
 import ctypes
 import math
 
+import numpy as np
+
 import torch
 
 from . import _lib
@@ -255,6 +257,21 @@ class Context:
                                       ctypes.byref(info))
         self._check(st, "predict", info.value)
         return mean, mse
+
+    def fisher(self, x, y, theta):
+        """Fisher information of theta = (sigma^2, beta, nu) at the locations:
+        a 3 x 3 float64 numpy array (FP64 whatever the precision policy)."""
+        x = _dev_f64(x, "x")
+        n = x.numel()
+        y = _dev_f64(y, "y", n)
+        self._sync_stream()
+        self._ensure_ws(n, FP64, True)
+        out = (ctypes.c_double * 9)()
+        info = ctypes.c_int64(0)
+        st = self._lib.exageo_fisher(self._h, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                     _lib.darr(theta), out, ctypes.byref(info))
+        self._check(st, "fisher", info.value)
+        return np.array(out[:], dtype=np.float64).reshape(3, 3)
 
     def mle(self, x, y, z, lb, ub, theta0=None, tol: float = 1e-4, max_iters: int = 0, method="dfo",
             precision="fp64"):

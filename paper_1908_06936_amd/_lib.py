@@ -31,7 +31,7 @@ EXPORTS = [
     "exageo_set_mixed_policy", "exageo_set_mixed_fp64_band", "exageo_set_dst_band", "exageo_set_distance", "exageo_last_error",
     "exageo_matern_cov",
     "exageo_simulate", "exageo_loglik",
-    "exageo_loglik_grad", "exageo_mle", "exageo_predict", "exageo_get_timings", "exageo_set_profiling",
+    "exageo_loglik_grad", "exageo_mle", "exageo_predict", "exageo_fisher", "exageo_get_timings", "exageo_set_profiling",
 ]
 
 _lib = None
@@ -78,6 +78,8 @@ def load():
     lib.exageo_loglik_grad.argtypes = [p, i64, p, p, p, pd, i32, pd, pd, pi64]
     lib.exageo_predict.restype = st
     lib.exageo_predict.argtypes = [p, i64, p, p, p, pd, i64, p, p, p, p, pi64]
+    lib.exageo_fisher.restype = st
+    lib.exageo_fisher.argtypes = [p, i64, p, p, pd, pd, pi64]
     lib.exageo_mle.restype = st
     lib.exageo_mle.argtypes = [p, i64, p, p, p, pd, pd, pd, d, i32, i32, i32, pd, pd, ctypes.POINTER(MleStats)]
     lib.exageo_get_timings.restype = ctypes.c_int

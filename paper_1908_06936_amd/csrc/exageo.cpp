@@ -916,3 +916,61 @@ exageo_status exageo_predict(exageo_ctx* c, int64_t n, const double* x, const do
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return EXAGEO_OK;
 }
+
+exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const double* y, const double theta[3],
+                            double fisher[9], int64_t* info) {
+  if (!c) return EXAGEO_EINVAL;
+  c->err.clear();
+  if (info) *info = 0;
+  if (n < 1 || !x || !y || !theta_ok(theta) || !fisher) return fail(c, EXAGEO_EINVAL, "fisher: invalid argument");
+  if (n > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n too large");
+  if (c->dst_band > 0) return fail(c, EXAGEO_EINVAL, "the Fisher information is computed for the exact covariance only");
+  if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
+  Plan p = make_plan(n, c->ts, 1, EXAGEO_FP64);
+  exageo_status st = ensure_ws(c, p);
+  if (st) return st;
+  c->plan = p;
+  std::memset(c->timings, 0, sizeof c->timings);
+  rec(c, 0);
+  // the observations do not enter I(theta): x stands in for them in the sort
+  st = prepare_locations(c, p, x, y, x);
+  if (st) return st;
+  rec(c, 1);
+  double ll = 0.0;
+  st = eval_sorted(c, p, theta, false, &ll, nullptr, info, true);
+  if (st) return st;
+  const int64_t nparts = exg::fisher_part_blocks(p.ts, p.NT);
+  const size_t full = (size_t)p.npad * (size_t)p.npad;
+  const size_t need = (3 * full + 5 * (size_t)nparts + 16) * 8;
+  double* buf = nullptr;
+  hipError_t e = hipMalloc((void**)&buf, need);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, EXAGEO_ENOMEM, "fisher: hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
+  }
+  const exg::TileMat M = tilemat(c, p);
+  double* Xd = at<double>(c, p.off_xd);
+  // L^-1 in place (the tile matrix then holds X = L^-1, lower-triangular tiles)
+  for (int64_t k = 0; k < p.NT; ++k)
+    exg::launch_trtri_step(M, Xd + k * p.ts * p.ts, at<double>(c, p.off_ptmp), k, p.n, c->stream);
+  double* Bb = buf;                // dSigma_beta, then B_beta
+  double* Mb = buf + full;         // X dSigma_j
+  double* Bn = buf + 2 * full;     // dSigma_nu, then B_nu
+  double* part = buf + 3 * full;   // partial sums of the traces and products
+  double* out = part + 5 * nparts;
+  const double* xs = at<double>(c, p.off_xs);
+  const double* ys = at<double>(c, p.off_ys);
+  const double* qt = at<double>(c, p.off_qt);
+  const double* cst = at<double>(c, p.off_cst);
+  exg::launch_fisher_param(M, 1, p.n, xs, ys, qt, cst, Bb, Mb, Bb, c->stream);
+  exg::launch_fisher_param(M, 2, p.n, xs, ys, qt, cst, Bn, Mb, Bn, c->stream);
+  exg::launch_fisher_reduce(Bb, Bn, p.ts, p.NT, p.n, cst, part, out, c->stream);
+  rec(c, 5);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(fisher, out, 9 * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  const hipError_t ef = hipFree(buf);
+  if (e != hipSuccess) return fail(c, EXAGEO_EDEVICE, "fisher: %s", hipGetErrorString(e));
+  if (ef != hipSuccess) return fail(c, EXAGEO_EDEVICE, "fisher: hipFree: %s", hipGetErrorString(ef));
+  return EXAGEO_OK;
+}

@@ -86,4 +86,12 @@ void launch_krige_mse(const TileMat& M, const double* Xd, const double* xs, cons
                       const double* xn, const double* yn, int64_t m, int64_t c0, int64_t ncols, const double* qt,
                       const double* cst, double* C, double* V, double* mse, hipStream_t s);
 
+// k_fisher.hip (X: the tile matrix holding L^-1; G, Mb, Bs, Bb, Bn: NT^2 full tiles each)
+int64_t fisher_part_blocks(int64_t ts, int64_t NT);
+void launch_fisher_param(const TileMat& X, int comp, int64_t nreal, const double* xs, const double* ys,
+                         const double* qt, const double* cst, double* G, double* Mb, double* Bs, hipStream_t s);
+// part: 5 fisher_part_blocks doubles; out: 9 doubles (device)
+void launch_fisher_reduce(const double* Bb, const double* Bn, int64_t ts, int64_t NT, int64_t nreal, const double* cst,
+                          double* part, double* out, hipStream_t s);
+
 }  // namespace exg
