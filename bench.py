@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a plain 1 GiB
 # device copy read and write 1 GiB.  Valid only for the kernel sources the
 # counters were taken on (fingerprint below); otherwise reported as null.
-TRAFFIC_BYTES_PER_LAUNCH = (4.9503e6 * 2.0 + 1.0333e6 * 1.0) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = (4.9498e6 * 2.0 + 1.0333e6 * 1.0) * 1024
 TRAFFIC_SOURCES = ("paper_1908_06936_amd/csrc/common.h", "paper_1908_06936_amd/csrc/k_gemm.hip")
-TRAFFIC_FINGERPRINT = "49435b141208c34851a45e161e7e31b1eaacc790"
+TRAFFIC_FINGERPRINT = "ada5aa0a89eaadf338d62f79c987f43139b9b28c"
 
 
 def traffic_bytes():
@@ -354,6 +354,20 @@ def main() -> int:
     t3 = time.perf_counter()
     result["kriging_m1000"] = {"mean_ms": 1e3 * (t2 - t1), "mean_and_mse_ms": 1e3 * (t3 - t2),
                                "note": "factorisation of the n = 40,000 covariance included"}
+    # Fisher information at theta (FP64; factorisation and L^-1 included)
+    ctx.fisher(X, Y, theta)  # warm-up (allocates its 3 n^2 doubles per call)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fish = ctx.fisher(X, Y, theta)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tf = ctx.timings()
+    result["fisher_information"] = {
+        "call_ms": 1e3 * (t2 - t1), "fisher_phase_ms": tf["grad_ms"], "product_flops": tf["fisher_flops"],
+        "phase_tflops": tf["fisher_flops"] / (tf["grad_ms"] * 1e-3) / 1e12,
+        "note": "phase = L^-1, the two derivative matrices, B_j = L^-1 dSigma_j L^-T, the reduction",
+        "I": fish.tolist()}
+    print("[bench] Fisher done", file=sys.stderr, flush=True)
     if args.no_mixed:
         if not args.no_cpu:
             result["cpu_baseline"] = cpu_baseline(n, theta, args.cpu_sample)

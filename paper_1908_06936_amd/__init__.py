@@ -155,7 +155,7 @@ class Context:
         m = self._lib.exageo_get_timings(self._h, buf, 24)
         keys = ["total_ms", "prep_ms", "gen_ms", "chol_ms", "update_kernel_ms", "update_flops", "solve_ms",
                 "grad_ms", "chol_flops", "update_launches", "precision", "frac_bf16", "frac_fp32", "update_steps",
-                "frac_fp64", "update_flops_fp32", "update_flops_bf16", "update_flops_fp64"]
+                "frac_fp64", "update_flops_fp32", "update_flops_bf16", "update_flops_fp64", "fisher_flops"]
         return {k: buf[i] for i, k in enumerate(keys[:m])}
 
     # ---------------------------------------------------------- operations

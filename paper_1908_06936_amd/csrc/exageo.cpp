@@ -969,6 +969,15 @@ exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const dou
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(fisher, out, 9 * 8, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && c->profiling) {
+    c->timings[0] = ev_ms(c, 0, 5);
+    c->timings[7] = ev_ms(c, 4, 5);
+    // MFMA flops of the two products per parameter over the R real 128-blocks:
+    // X G (row block g runs over (g + 1) 128 columns of X) and M X^T (lower
+    // block pairs (g, h), h <= g, over (h + 1) 128 columns)
+    const double R = (double)((p.n + BLKH - 1) / BLKH), b3 = 2.0 * BLKH * BLKH * BLKH;
+    c->timings[18] = 2.0 * b3 * (R * R * (R + 1.0) / 2.0 + R * (R + 1.0) * (R + 2.0) / 6.0);
+  }
   const hipError_t ef = hipFree(buf);
   if (e != hipSuccess) return fail(c, EXAGEO_EDEVICE, "fisher: %s", hipGetErrorString(e));
   if (ef != hipSuccess) return fail(c, EXAGEO_EDEVICE, "fisher: hipFree: %s", hipGetErrorString(ef));
