@@ -32,7 +32,7 @@ def _err(I, ref):
 
 @pytest.mark.parametrize("n,ts,th", [(700, 256, [1.0, 0.1, 0.8]), (1000, 384, [1.5, 0.05, 1.3]),
                                      (300, 128, [0.8, 0.2, 0.5]), (100, 128, [1.2, 0.07, 2.1]),
-                                     (1300, 512, [0.6, 0.03, 0.9])])
+                                     (1300, 512, [0.6, 0.03, 0.9]), (256, 128, [1.0, 0.1, 1.0])])
 def test_fisher_vs_oracle(orc, exa, n, ts, th):
     # several tiles with a ragged last one, a single padded tile (n = 100)
     x, y = inputgen.uniform(n, seed=200 + n)
@@ -42,6 +42,15 @@ def test_fisher_vs_oracle(orc, exa, n, ts, th):
     print(f"n={n} ts={ts}: max scaled error {_err(I, ref):.2e}")
     assert _err(I, ref) <= TOL
     np.testing.assert_array_equal(I, I.T)
+
+
+def test_fisher_single_point(exa):
+    # n = 1: only sigma^2 is identifiable, I = diag(1 / (2 sigma^4), 0, 0)
+    ctx = exa.Context(ts=128)
+    I = ctx.fisher(dev([0.3]), dev([0.4]), [1.5, 0.1, 0.8])
+    ref = np.zeros((3, 3))
+    ref[0, 0] = 1.0 / (2 * 1.5 ** 2)
+    np.testing.assert_allclose(I, ref, rtol=1e-15, atol=0)
 
 
 def test_fisher_ignores_precision_policy_and_rejects_dst(orc, exa):
