@@ -71,9 +71,10 @@ def mle_study(args) -> int:
     * n = 400 (20 x 20 jittered grid, theta = (1, 0.1, 0.5)): one l and the
       derivative-free MLE from the lower bound, as in the paper's example.
     * n = 40,000 (200 x 200 jittered grid, true theta = (1, 0.1, 0.5) and
-      (1, 0.1, 0.8), start (0.5, 0.3, 0.5)): FP64 derivative-free vs FP64 and
-      mixed-precision L-BFGS-B, wall clock, theta-hat and l(theta-hat)
-      re-evaluated in FP64.
+      (1, 0.1, 0.8), start (0.5, 0.3, 0.5)): FP64 derivative-free vs FP64
+      L-BFGS-B and the mixed-precision L-BFGS-B search with an FP64 finish
+      (--mle-all adds plain mixed L-BFGS-B and mixed derivative-free), wall
+      clock, theta-hat and l(theta-hat) re-evaluated in FP64.
     * n = side^2 (default 160,000): one FP64 l, one FP64 (l, grad l) and one
       mixed (l, grad l) at the true theta (the full estimators at this size
       take hours of derivative-free evaluations).
@@ -115,11 +116,14 @@ def mle_study(args) -> int:
     # (nu = 0.8) field; evaluation caps keep each run within a few minutes
     lb, ub, th0 = [0.01, 0.01, 0.1], [5.0, 2.0, 3.0], [0.5, 0.3, 0.5]
     out["n40000_grid"] = {}
-    for th_true in ([1.0, 0.1, 0.5], [1.0, 0.1, 0.8]):
+    for th_true in [[1.0, 0.1, nu] for nu in args.mle_nus]:
         ctx, X, Y, Z = field(200, th_true, 1, 768)
         runs = {}
-        for label, meth, prec, cap in (("fp64_dfo", "dfo", "fp64", 400), ("fp64_lbfgsb", "lbfgsb", "fp64", 80),
-                                       ("mixed_lbfgsb", "lbfgsb", "mixed", 80), ("mixed_dfo", "dfo", "mixed", 400)):
+        estimators = [("fp64_dfo", "dfo", "fp64", 400), ("fp64_lbfgsb", "lbfgsb", "fp64", 80),
+                      ("mixed_lbfgsb_fp64_finish", "lbfgsb_fp64_finish", "mixed", 80)]
+        if args.mle_all:
+            estimators += [("mixed_lbfgsb", "lbfgsb", "mixed", 80), ("mixed_dfo", "dfo", "mixed", 400)]
+        for label, meth, prec, cap in estimators:
             # mixed: FP32 off-diagonal tiles with the FP64 band at 0.5 beta, no BF16
             ctx.set_mixed_policy(0.0, 0.5)
             t0 = time.perf_counter()
@@ -150,6 +154,9 @@ def mle_study(args) -> int:
 
     # large n: single evaluations
     m = args.big_n_side
+    if m <= 0:
+        print(json.dumps(out))
+        return 0
     ctx, X, Y, Z = field(m, th_true, 2, 768)
     ctx.set_mixed_policy(0.0, 0.5)
     big = {"n": m * m, "mixed_policy": "FP32 off-diagonal, FP64 band 0.5 beta"}
@@ -236,7 +243,10 @@ def main() -> int:
     ap.add_argument("--mle-study", action="store_true",
                     help="instead of the throughput step: the MLE comparisons (FP64 derivative-free vs "
                          "gradient-based and mixed precision) and single evaluations at n = 160,000")
-    ap.add_argument("--big-n-side", type=int, default=400, help="grid side of the large single evaluations")
+    ap.add_argument("--big-n-side", type=int, default=400,
+                    help="grid side of the large single evaluations (0: skip them)")
+    ap.add_argument("--mle-all", action="store_true", help="also the plain mixed-precision estimators")
+    ap.add_argument("--mle-nus", type=float, nargs="+", default=[0.5, 0.8], help="true nu of the n = 40,000 fields")
     ap.add_argument("--precision-study", action="store_true",
                     help="instead of the throughput step: FP64 vs mixed-precision l on a 300 x 300 jittered grid")
     args = ap.parse_args()

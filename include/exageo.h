@@ -60,6 +60,11 @@ typedef int32_t exageo_status;
 /* optimiser of exageo_mle */
 #define EXAGEO_DFO 0    /* derivative-free bounded search on l(theta)         */
 #define EXAGEO_LBFGSB 1 /* bounded quasi-Newton on (l, grad l)                */
+/* with EXAGEO_MIXED: the quasi-Newton search on the mixed-precision (l, grad l)
+ * until its accepted l improve by less than 1e-6 |l| (the level of the mixed
+ * error), then the same search in FP64 from there (ending after three
+ * accepted steps in a row below tol); other precisions: as EXAGEO_LBFGSB */
+#define EXAGEO_LBFGSB_FP64_FINISH 2
 
 typedef struct exageo_ctx exageo_ctx;
 
@@ -70,6 +75,9 @@ typedef struct {
   double total_s;       /* wall time of the whole estimation             */
   double per_eval_s;    /* total_s / (n_evals + n_grad_evals)            */
   exageo_status status; /* EXAGEO_OK or EXAGEO_ENOCONV                    */
+  int64_t n_fp64_finish_evals; /* (l, grad l) evaluations of the FP64 finish
+                                  (EXAGEO_LBFGSB_FP64_FINISH; included in
+                                  n_grad_evals)                          */
 } exageo_mle_stats;
 
 /* Create a context bound to HIP device `device`, tile size `ts` (a multiple of
@@ -195,8 +203,11 @@ exageo_status exageo_fisher(exageo_ctx *ctx, int64_t n, const double *x, const d
  * theta0 = NULL starts the derivative-free method at lb, as the paper's
  * optimisation list does, and the gradient method at sqrt(lb * ub).
  * tol: stop when successive accepted l values differ by less than tol;
- * max_iters: limit on evaluations, 0 = unlimited.  method EXAGEO_DFO or
- * EXAGEO_LBFGSB.  Points where the factorisation fails count as l = -inf.
+ * max_iters: limit on evaluations, 0 = unlimited.  method EXAGEO_DFO,
+ * EXAGEO_LBFGSB or EXAGEO_LBFGSB_FP64_FINISH (the workspace must then hold
+ * both the mixed and the FP64 plan with the gradient: the larger of the two
+ * exageo_workspace_bytes).  Points where the factorisation fails count as
+ * l = -inf.
  * Returns ENOCONV (results still written) when max_iters stops it. */
 exageo_status exageo_mle(exageo_ctx *ctx, int64_t n, const double *x, const double *y, const double *z,
                          const double lb[3], const double ub[3], const double *theta0, double tol,

@@ -21,9 +21,11 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DFO, EINVAL, ENOCONV, ENOMEM, ENOTPD, FP64, LBFGSB, MIXED, OK, STATUS_NAMES
+from ._lib import (DFO, EINVAL, ENOCONV, ENOMEM, ENOTPD, FP64, LBFGSB, LBFGSB_FP64_FINISH, MIXED, OK,
+                   STATUS_NAMES)
 
-__all__ = ["Context", "ExaGeoError", "NotPositiveDefinite", "ExaGeoLoglik", "FP64", "MIXED", "DFO", "LBFGSB"]
+__all__ = ["Context", "ExaGeoError", "NotPositiveDefinite", "ExaGeoLoglik", "FP64", "MIXED", "DFO", "LBFGSB",
+           "LBFGSB_FP64_FINISH"]
 
 
 class ExaGeoError(RuntimeError):
@@ -50,6 +52,8 @@ def _method(method) -> int:
         return DFO
     if method in (LBFGSB, "lbfgsb", "l-bfgs-b"):
         return LBFGSB
+    if method in (LBFGSB_FP64_FINISH, "lbfgsb_fp64_finish"):
+        return LBFGSB_FP64_FINISH
     raise ValueError(f"unknown method {method!r}")
 
 
@@ -282,7 +286,9 @@ class Context:
         y, z = _dev_f64(y, "y", n), _dev_f64(z, "z", n)
         prec, meth = _prec(precision), _method(method)
         self._sync_stream()
-        self._ensure_ws(n, prec, meth == LBFGSB)
+        self._ensure_ws(n, prec, meth != DFO)
+        if meth == LBFGSB_FP64_FINISH:
+            self._ensure_ws(n, FP64, True)  # the finish runs the FP64 plan in the same workspace
         th = (ctypes.c_double * 3)()
         ll = ctypes.c_double(0.0)
         stats = _lib.MleStats()
@@ -294,7 +300,8 @@ class Context:
             self._check(st, "mle")
         out = {"n_evals": stats.n_evals, "n_grad_evals": stats.n_grad_evals, "iters": stats.iters,
                "total_s": stats.total_s, "per_eval_s": stats.per_eval_s,
-               "status": STATUS_NAMES.get(stats.status, stats.status)}
+               "status": STATUS_NAMES.get(stats.status, stats.status),
+               "n_fp64_finish_evals": stats.n_fp64_finish_evals}
         return [th[0], th[1], th[2]], ll.value, out
 
 

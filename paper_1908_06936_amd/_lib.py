@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libexageo.so")
 OK, EINVAL, ENOTPD, ENOMEM, EDEVICE, ENOCONV = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 EUCLIDEAN, GREAT_CIRCLE = 0, 1
-DFO, LBFGSB = 0, 1
+DFO, LBFGSB, LBFGSB_FP64_FINISH = 0, 1, 2
 
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOTPD: "ENOTPD", ENOMEM: "ENOMEM",
                 EDEVICE: "EDEVICE", ENOCONV: "ENOCONV"}
@@ -23,7 +23,8 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOTPD: "ENOTPD", ENOMEM: "ENOMEM",
 
 class MleStats(ctypes.Structure):
     _fields_ = [("n_evals", ctypes.c_int64), ("n_grad_evals", ctypes.c_int64), ("iters", ctypes.c_int64),
-                ("total_s", ctypes.c_double), ("per_eval_s", ctypes.c_double), ("status", ctypes.c_int32)]
+                ("total_s", ctypes.c_double), ("per_eval_s", ctypes.c_double), ("status", ctypes.c_int32),
+                ("n_fp64_finish_evals", ctypes.c_int64)]
 
 
 EXPORTS = [

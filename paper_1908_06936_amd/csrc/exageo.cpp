@@ -793,23 +793,29 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
   c->err.clear();
   if (n < 1 || !x || !y || !z || !lb || !ub || !theta_hat || !loglik_hat || !(tol >= 0.0) || max_iters < 0)
     return fail(c, EXAGEO_EINVAL, "mle: invalid argument");
-  if (method != EXAGEO_DFO && method != EXAGEO_LBFGSB) return fail(c, EXAGEO_EINVAL, "unknown method");
+  if (method != EXAGEO_DFO && method != EXAGEO_LBFGSB && method != EXAGEO_LBFGSB_FP64_FINISH)
+    return fail(c, EXAGEO_EINVAL, "unknown method");
   if (precision != EXAGEO_FP64 && precision != EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "unknown precision");
   for (int k = 0; k < 3; ++k) {
     if (!theta_ok(lb) || !theta_ok(ub) || lb[k] > ub[k]) return fail(c, EXAGEO_EINVAL, "mle: bad bounds");
     if (theta0 && (!(theta0[k] >= lb[k]) || !(theta0[k] <= ub[k]))) return fail(c, EXAGEO_EINVAL, "theta0 outside bounds");
   }
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
-  const bool want_grad = method == EXAGEO_LBFGSB;
+  const bool want_grad = method != EXAGEO_DFO;
   if (precision == EXAGEO_MIXED && c->dst_band > 0)
     return fail(c, EXAGEO_EINVAL, "the DST approximation runs in FP64 only");
+  // mixed search with an FP64 finish: both plans live in one workspace, in turn
+  const bool finish64 = method == EXAGEO_LBFGSB_FP64_FINISH && precision == EXAGEO_MIXED;
   Plan p = make_plan(n, c->ts, want_grad, precision);
   p.dst = c->dst_band;
-  exageo_status st = ensure_ws(c, p);
+  Plan p64 = make_plan(n, c->ts, 1, EXAGEO_FP64);
+  p64.dst = c->dst_band;
+  exageo_status st = ensure_ws(c, finish64 && p64.bytes > p.bytes ? p64 : p);
   if (st) return st;
   c->plan = p;
   st = prepare_locations(c, p, x, y, z);
   if (st) return st;
+  const Plan* cur = &p;
   const auto t0 = std::chrono::steady_clock::now();
   int64_t nev = 0, ngev = 0;
   exageo_status first_err = EXAGEO_OK;
@@ -817,7 +823,7 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
   exg::Objective obj = [&](const double th[3], bool g, double* f, double gr[3]) -> bool {
     double ll = -INFINITY;
     int64_t inf = 0;
-    exageo_status s = eval_sorted(c, p, th, g, &ll, gr, &inf, !checked_box);
+    exageo_status s = eval_sorted(c, *cur, th, g, &ll, gr, &inf, !checked_box);
     checked_box = true;
     if (g) ++ngev;
     else ++nev;
@@ -835,8 +841,34 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
   // method, whose first step would otherwise sit on the flat face beta -> 0
   for (int k = 0; k < 3; ++k)
     th0[k] = theta0 ? theta0[k] : (method == EXAGEO_DFO ? lb[k] : std::sqrt(lb[k] * ub[k]));
-  exg::MleResult res = method == EXAGEO_DFO ? exg::maximize_dfo(obj, lb, ub, th0, tol, max_iters)
-                                            : exg::maximize_lbfgsb(obj, lb, ub, th0, tol, max_iters);
+  exg::MleResult res;
+  int64_t nfinish = 0;
+  if (method == EXAGEO_DFO) {
+    res = exg::maximize_dfo(obj, lb, ub, th0, tol, max_iters);
+  } else if (!finish64) {
+    res = exg::maximize_lbfgsb(obj, lb, ub, th0, tol, max_iters);
+  } else {
+    // the mixed score carries an error of the order of the mixed l's (its
+    // factor is a perturbed Sigma's), which stalls the search near the optimum:
+    // search in mixed precision while l still improves by more than 1e-6 |l|
+    // (at most half the budget, 40 evaluations when unlimited), then finish
+    // in FP64 from the best mixed point.  The finish starts without curvature
+    // pairs, so one small first step does not end it: three in a row do
+    const int cap1 = max_iters > 0 ? std::max(1, max_iters / 2) : 40;
+    const exg::MleResult r1 = exg::maximize_lbfgsb(obj, lb, ub, th0, tol, cap1, 1e-6);
+    if (first_err != EXAGEO_OK) return first_err;
+    double th1[3];
+    for (int k = 0; k < 3; ++k) th1[k] = std::isfinite(r1.f) ? r1.theta[k] : th0[k];
+    cur = &p64;
+    c->plan = p64;
+    st = prepare_locations(c, p64, x, y, z);
+    if (st) return st;
+    const int64_t used = nev + ngev, before = ngev;
+    const int cap2 = max_iters > 0 ? (int)std::max<int64_t>(1, max_iters - used) : 0;
+    res = exg::maximize_lbfgsb(obj, lb, ub, th1, tol, cap2, 0.0, 3);
+    res.iters += r1.iters;
+    nfinish = ngev - before;
+  }
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (first_err != EXAGEO_OK) return first_err;
   for (int k = 0; k < 3; ++k) theta_hat[k] = res.theta[k];
@@ -848,6 +880,7 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
     stats->total_s = secs;
     stats->per_eval_s = (nev + ngev) ? secs / (double)(nev + ngev) : 0.0;
     stats->status = res.converged ? EXAGEO_OK : EXAGEO_ENOCONV;
+    stats->n_fp64_finish_evals = nfinish;
   }
   if (!std::isfinite(res.f)) return fail(c, EXAGEO_ENOTPD, "no feasible point found");
   return res.converged ? EXAGEO_OK : fail(c, EXAGEO_ENOCONV, "max_iters reached before tol");

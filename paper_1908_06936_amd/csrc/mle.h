@@ -31,8 +31,9 @@ MleResult maximize_dfo(const Objective& f, const double lb[3], const double ub[3
 // ones, and a projected backtracking (Armijo) line search keeps the iterate in
 // the box (after the bounded L-BFGS of Byrd, Lu, Nocedal & Zhu, SIAM J. Sci.
 // Comput. 16, 1995, without its generalised Cauchy point).  Stops when
-// successive accepted l differ by less than tol, or after max_evals.
+// successive accepted l differ by less than tol + rtol |l| (patience times in a
+// row), or after max_evals.
 MleResult maximize_lbfgsb(const Objective& f, const double lb[3], const double ub[3], const double theta0[3],
-                          double tol, int max_evals);
+                          double tol, int max_evals, double rtol = 0.0, int patience = 1);
 
 }  // namespace exg

@@ -166,7 +166,7 @@ MleResult maximize_dfo(const Objective& obj, const double lb[3], const double ub
 
 // ------------------------------------------------------- projected L-BFGS
 MleResult maximize_lbfgsb(const Objective& obj, const double lb[3], const double ub[3], const double theta0[3],
-                          double tol, int max_evals) {
+                          double tol, int max_evals, double rtol, int patience) {
   const Box box = log_box(lb, ub);
   MleResult res{};
   res.f = -std::numeric_limits<double>::infinity();
@@ -204,6 +204,7 @@ MleResult maximize_lbfgsb(const Objective& obj, const double lb[3], const double
     }
   }
   int64_t it = 0;
+  int small = 0;  // consecutive accepted steps below the tolerance
   bool conv = false;
   while (std::isfinite(f) && !hard && budget_left()) {
     ++it;
@@ -311,7 +312,8 @@ MleResult maximize_lbfgsb(const Objective& obj, const double lb[3], const double
       g[k] = gn[k];
     }
     f = fn;
-    if (df < tol) {
+    small = df < tol + rtol * std::fabs(f) ? small + 1 : 0;
+    if (small >= patience) {
       conv = true;
       break;
     }

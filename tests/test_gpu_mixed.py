@@ -225,3 +225,28 @@ def test_mixed_grad_fp64_band_vs_oracle(orc, exa):
     # error; the FP32 inverse factor outside it keeps the rest
     assert errs[0.5] < errs[0.0]
     assert errs[0.5] <= 1e-5
+
+
+def test_mle_mixed_search_with_fp64_finish(exa):
+    # 48 x 48 jittered grid, theta = (1, 0.1, 0.5): the mixed-precision search
+    # followed by an FP64 finish reaches the FP64 L-BFGS-B optimum to 1e-6 of l
+    import inputgen
+
+    x, y = inputgen.jittered_grid(48, seed=4)
+    n = x.size
+    ctx = exa.Context(ts=256)
+    th_true = [1.0, 0.1, 0.5]
+    e = torch.as_tensor(inputgen.normals(n, seed=4), device="cuda")
+    X, Y = dev(x), dev(y)
+    Z = ctx.simulate(X, Y, th_true, e)
+    lb, ub, th0 = [0.01, 0.01, 0.1], [5.0, 2.0, 3.0], [0.5, 0.3, 0.5]
+    th64, ll64, st64 = ctx.mle(X, Y, Z, lb, ub, theta0=th0, tol=1e-7, method="lbfgsb", precision="fp64")
+    ctx.set_mixed_policy(0.0)
+    thm, llm, stm = ctx.mle(X, Y, Z, lb, ub, theta0=th0, tol=1e-7, method="lbfgsb_fp64_finish",
+                            precision="mixed")
+    print(f"fp64 {th64} {ll64} {st64}\nmixed+finish {thm} {llm} {stm}")
+    assert st64["status"] == "OK" and stm["status"] == "OK"
+    assert 0 < stm["n_fp64_finish_evals"] < stm["n_grad_evals"]
+    # the reported value is an FP64 likelihood at the returned point
+    assert ctx.loglik(X, Y, Z, thm) == llm
+    assert abs(llm - ll64) <= 1e-6 * abs(ll64)
