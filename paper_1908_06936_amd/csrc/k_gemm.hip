@@ -222,8 +222,43 @@ __global__ void k_copy_back(TileMat M, const double* __restrict__ P, int64_t cou
   tptr(M, i, j)[o] = P[e];
 }
 
+// ------------------------------------------ tile transposition
+// Every lower tile of the tile matrix transposed in place, so that the columns
+// of X = L^-1 become contiguous rows for the LAUUM below (both of its operands
+// are then read along their contiguous index).  One workgroup swaps the 64 x 64
+// blocks (a, b) and (b, a), a <= b, of one tile through LDS.
+constexpr int TB = 64;
+__global__ __launch_bounds__(256) void k_transpose_tiles(TileMat M, int64_t npt, int64_t nb) {
+  __shared__ double s1[TB][TB + 1];
+  __shared__ double s2[TB][TB + 1];
+  const int64_t g = blockIdx.x;
+  if (g >= nb) return;
+  const int64_t ts = M.ts;
+  int64_t I, J, bq, aq;
+  tri_decode(g / npt, &I, &J);
+  tri_decode(g % npt, &bq, &aq);  // aq <= bq
+  double* T = tptr(M, I, J);
+  const int64_t ra = aq * TB, rb = bq * TB;
+  for (int e = threadIdx.x; e < TB * TB; e += 256) {
+    const int r = e & (TB - 1), c = e >> 6;
+    s1[c][r] = T[(ra + r) + (rb + c) * ts];
+    if (aq != bq) s2[c][r] = T[(rb + r) + (ra + c) * ts];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < TB * TB; e += 256) {
+    const int r = e & (TB - 1), c = e >> 6;
+    if (aq != bq) {
+      T[(ra + r) + (rb + c) * ts] = s2[r][c];
+      T[(rb + r) + (ra + c) * ts] = s1[r][c];
+    } else {
+      T[(ra + r) + (ra + c) * ts] = s1[r][c];
+    }
+  }
+}
+
 // ------------------------------------------ fused LAUUM + score contraction
-// Block (I, J, u, v) of W = X^T X with X = L^-1 (lower tiles, in place of L),
+// Block (I, J, u, v) of W = X^T X with X = L^-1 (lower tiles, in place of L,
+// each tile transposed by k_transpose_tiles),
 // followed by g_m += sum (w_ij (a_i a_j - W_ij) / 2) dSigma_m(i, j) over its
 // entries, w = 2 below the diagonal, 1 on it, 0 above and on padding.
 // part[3 b + m] receives the block's sums (zeros for skipped blocks).
@@ -252,19 +287,20 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract(TileMat M, int T, int
   // One virtual k range over the tiles K = I, ..., NT-1 of tile columns I and
   // J: first rows r0.. of tile row I (X_II is lower triangular, so rows above
   // u*128 of its column block u are zero), then every row of the tiles below.
+  // Transposed tiles: X(K, I)[k, m] sits at k ts + m of tile (K, I).
   const int64_t r0 = (int64_t)u * BLK, c0 = (int64_t)v * BLK;
   const int64_t L0 = ts - r0;
   auto ap = [=](int k0) -> const double* {
-    if (k0 < L0) return tptr(M, I, I) + r0 + k0 + r0 * ts;
+    if (k0 < L0) return tptr(M, I, I) + r0 + (r0 + k0) * ts;
     const int64_t kk = k0 - L0, K = I + 1 + kk / ts;
-    return tptr(M, K, I) + (kk % ts) + r0 * ts;
+    return tptr(M, K, I) + r0 + (kk % ts) * ts;
   };
   auto bp = [=](int k0) -> const double* {
-    if (k0 < L0) return tptr(M, I, J) + r0 + k0 + c0 * ts;
+    if (k0 < L0) return tptr(M, I, J) + c0 + (r0 + k0) * ts;
     const int64_t kk = k0 - L0, K = I + 1 + kk / ts;
-    return tptr(M, K, J) + (kk % ts) + c0 * ts;
+    return tptr(M, K, J) + c0 + (kk % ts) * ts;
   };
-  gemm_core<true, true>(ap, ts, bp, ts, (int)(L0 + (NT - 1 - I) * ts), acc, sm);
+  gemm_core<false, false>(ap, ts, bp, ts, (int)(L0 + (NT - 1 - I) * ts), acc, sm);
   contract_block64(acc, I * ts + r0, J * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
 }
 
@@ -362,6 +398,8 @@ int64_t lauum_blocks(int64_t ts, int64_t NT) {
 void launch_lauum_contract(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* av,
                            const double* qt, const double* cst, double* part, hipStream_t s) {
   const int T = (int)(M.ts / BLK);
+  const int64_t t64 = M.ts / TB, npt = t64 * (t64 + 1) / 2, ntr = M.NT * (M.NT + 1) / 2 * npt;
+  hipLaunchKernelGGL(k_transpose_tiles, dim3((unsigned)ntr), dim3(256), 0, s, M, npt, ntr);
   const int64_t nb = lauum_blocks(M.ts, M.NT);
   hipLaunchKernelGGL(k_lauum_contract, dim3((unsigned)nb), dim3(256), 0, s, M, T, nreal, xs, ys, av, qt, cst, part,
                      nb);
