@@ -161,21 +161,51 @@ def matern_dcov(x, y, theta, comp: int) -> np.ndarray:
     return out
 
 
-def fisher(x, y, theta) -> np.ndarray:
+def fisher(x, y, theta, nugget: float = 0.0) -> np.ndarray:
     """Fisher information of theta = (sigma^2, beta, nu) for the zero-mean
     Gaussian field observed at (x, y) (the exact_fisher function of the
     package's API table, Section 3): the expected negative Hessian of eq. (2),
         I_jk = tr(Sigma^-1 dSigma_j Sigma^-1 dSigma_k) / 2.
     With A_j = Sigma^-1 dSigma_j (a library solve used as a step) the trace is
-    the sum of the elementwise product of A_j and A_k^T."""
+    the sum of the elementwise product of A_j and A_k^T.  A fixed nugget tau^2
+    adds tau^2 I to Sigma and nothing to its theta-derivatives."""
     x, y, th = _f64(x), _f64(y), _f64(theta)
-    S = matern_cov(x, y, th)
+    S = matern_cov_nugget(x, y, th, nugget)
     A = [np.linalg.solve(S, matern_dcov(x, y, th, k)) for k in range(3)]
     I = np.empty((3, 3))
     for j in range(3):
         for k in range(3):
             I[j, k] = 0.5 * np.sum(A[j] * A[k].T)
     return I
+
+
+def matern_cov_nugget(x, y, theta, nugget: float) -> np.ndarray:
+    """Sigma(theta) + tau^2 I: the Matern covariance (eq. 3) of a field observed
+    with independent noise of variance tau^2 (the nugget effect the package's
+    kernels can include, Section 6); coincident distinct locations share sigma^2,
+    only each observation's own variance gains tau^2."""
+    S = matern_cov(x, y, theta)
+    if nugget:
+        S[np.diag_indices_from(S)] += nugget
+    return S
+
+
+def loglik_grad_nugget(x, y, z, theta, nugget: float):
+    """(l, grad l) of eq. (2) for Sigma(theta) + tau^2 I with tau^2 fixed:
+    dense library factorisation and inverse as steps,
+        g_k = a^T dSigma_k a / 2 - tr(Sigma^-1 dSigma_k) / 2,  a = Sigma^-1 z
+    (the nugget is constant in theta, so the derivative matrices are those of
+    the Matern part)."""
+    x, y, z, th = _f64(x), _f64(y), _f64(z), _f64(theta)
+    S = matern_cov_nugget(x, y, th, nugget)
+    ll = loglik_from_factor(np.linalg.cholesky(S), z)
+    Si = np.linalg.inv(S)
+    a = Si @ z
+    grad = np.empty(3)
+    for k in range(3):
+        dS = matern_dcov(x, y, th, k)
+        grad[k] = 0.5 * a @ dS @ a - 0.5 * np.sum(Si * dS)
+    return ll, grad
 
 
 def cholesky_packed(x, y, theta) -> np.ndarray:
@@ -209,19 +239,24 @@ def unpack_lower(Lp: np.ndarray, n: int) -> np.ndarray:
     return L
 
 
-def predict(x, y, z, theta, xn, yn):
+def predict(x, y, z, theta, xn, yn, nugget: float = 0.0):
     """Kriging at new locations (the conditional distribution of the Gaussian
     field given the data, paper Section 4 and Section 5): with c_i the vector
     of covariances between new point i and the observed points,
         mean_i = c_i^T Sigma^-1 z,   mse_i = sigma^2 - c_i^T Sigma^-1 c_i,
     evaluated through the oracle's own Cholesky factor L (Sigma = L L^T) as
     (L^-1 c_i)^T (L^-1 z) and sigma^2 - |L^-1 c_i|^2; the triangular solves are
-    a library routine used as a step.  Returns (mean, mse)."""
+    a library routine used as a step.  With a nugget tau^2 the observations
+    carry independent noise: Sigma gains tau^2 I (factored by LAPACK), c_i does
+    not (the prediction is of the noise-free field).  Returns (mean, mse)."""
     import scipy.linalg
 
     x, y, z, th, xn, yn = _f64(x), _f64(y), _f64(z), _f64(theta), _f64(xn), _f64(yn)
     n, m = x.size, xn.size
-    L = unpack_lower(cholesky_packed(x, y, th), n)
+    if nugget:
+        L = np.linalg.cholesky(matern_cov_nugget(x, y, th, nugget))
+    else:
+        L = unpack_lower(cholesky_packed(x, y, th), n)
     S = matern_cov(np.concatenate([x, xn]), np.concatenate([y, yn]), th)
     C = S[:n, n:]
     v = scipy.linalg.solve_triangular(L, z, lower=True)

@@ -594,3 +594,77 @@ def test_fisher_is_the_hessian_of_the_expected_loglik(orc):
     I = orc.fisher(x, y, th0)
     scale = np.sqrt(np.outer(np.diag(I), np.diag(I)))
     assert np.max(np.abs(-H - I) / scale) < 1e-7
+
+
+# ------------------------------------------------------------------- nugget
+def test_nugget_zero_is_the_unblocked_oracle(orc):
+    x, y = inputgen.uniform(180, seed=33)
+    th = [1.1, 0.09, 1.3]
+    z = orc.simulate(x, y, th, inputgen.normals(180, seed=33))
+    l0, g0 = orc.loglik_grad(x, y, z, th)
+    l1, g1 = orc.loglik_grad_nugget(x, y, z, th, 0.0)
+    assert l1 == pytest.approx(l0, rel=1e-12)
+    np.testing.assert_allclose(g1, g0, rtol=1e-9)
+
+
+def test_nugget_white_noise_limit(orc):
+    # beta so small that every off-diagonal covariance underflows: Sigma = (s2 + t2) I
+    s2, t2 = 1.3, 0.4
+    x, y = inputgen.jittered_grid(10, seed=2)
+    z = inputgen.normals(x.size, seed=2)
+    th = [s2, 1e-5, 0.5]
+    v = s2 + t2
+    ll, g = orc.loglik_grad_nugget(x, y, z, th, t2)
+    assert ll == pytest.approx(-0.5 * (x.size * (LN2PI + math.log(v)) + z @ z / v), rel=1e-13)
+    # d/dsigma^2 = (|z|^2 / v - n) / (2 v); the range and smoothness have no effect
+    assert g[0] == pytest.approx((z @ z / v - x.size) / (2 * v), rel=1e-12)
+    assert g[1] == 0.0 and g[2] == 0.0
+    I = orc.fisher(x, y, th, nugget=t2)
+    assert I[0, 0] == pytest.approx(x.size / (2 * v * v), rel=1e-12)
+
+
+def test_nugget_gradient_central_differences(orc):
+    x, y = inputgen.uniform(120, seed=8)
+    th, t2 = np.array([0.9, 0.12, 0.7]), 0.25
+    z = orc.simulate(x, y, th, inputgen.normals(120, seed=8))
+    _, g = orc.loglik_grad_nugget(x, y, z, th, t2)
+    for k in range(3):
+        h = 1e-6 * th[k]
+        e = np.eye(3)[k] * h
+        fd = (orc.loglik_grad_nugget(x, y, z, th + e, t2)[0] - orc.loglik_grad_nugget(x, y, z, th - e, t2)[0]) / (2 * h)
+        assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-6)
+
+
+def test_nugget_fisher_is_the_hessian_of_the_expected_loglik(orc):
+    x, y = inputgen.uniform(100, seed=19)
+    th0, t2 = np.array([1.0, 0.1, 1.1]), 0.3
+    S0 = orc.matern_cov_nugget(x, y, th0, t2)
+
+    def f(th):
+        S = orc.matern_cov_nugget(x, y, th, t2)
+        return -0.5 * (np.linalg.slogdet(S)[1] + np.trace(np.linalg.solve(S, S0)))
+
+    def hess(rel):
+        h = rel * th0
+        H = np.empty((3, 3))
+        for j in range(3):
+            for k in range(3):
+                ej, ek = np.eye(3)[j] * h[j], np.eye(3)[k] * h[k]
+                H[j, k] = (f(th0 + ej + ek) - f(th0 + ej - ek) - f(th0 - ej + ek)
+                           + f(th0 - ej - ek)) / (4 * h[j] * h[k])
+        return H
+
+    H = (4 * hess(1e-3) - hess(2e-3)) / 3
+    I = orc.fisher(x, y, th0, nugget=t2)
+    scale = np.sqrt(np.outer(np.diag(I), np.diag(I)))
+    assert np.max(np.abs(-H - I) / scale) < 1e-7
+    # the variance entry no longer has the nugget-free closed form
+    assert abs(I[0, 0] - x.size / (2 * th0[0] ** 2)) > 1e-3 * I[0, 0]
+
+
+def test_nugget_predict_single_observation(orc):
+    # one observation z at s: mean at s = s2 z / (s2 + t2), mse = s2 t2 / (s2 + t2)
+    s2, t2, z = 1.4, 0.6, 0.9
+    mean, mse = orc.predict([0.3], [0.4], [z], [s2, 0.1, 0.8], [0.3], [0.4], nugget=t2)
+    assert mean[0] == pytest.approx(s2 * z / (s2 + t2), rel=1e-14)
+    assert mse[0] == pytest.approx(s2 * t2 / (s2 + t2), rel=1e-14)
