@@ -128,6 +128,16 @@ exageo_status exageo_set_mixed_fp64_band(exageo_ctx *ctx, double fp64_band_facto
 enum { EXAGEO_EUCLIDEAN = 0, EXAGEO_GREAT_CIRCLE = 1 };
 exageo_status exageo_set_distance(exageo_ctx *ctx, int metric);
 
+/* Nugget effect (the paper's closing section: the package's kernels can
+ * include one): each observation carries independent noise of variance
+ * tau2 >= 0, so Sigma(theta) gains tau2 on its diagonal (coincident distinct
+ * locations still share sigma2 only).  tau2 is fixed, not estimated; the
+ * theta-derivatives, hence the score and the Fisher information, are those of
+ * the Matern part, and kriging predicts the noise-free field (no tau2 in the
+ * new-to-observed covariances, mse = sigma2 - c^T Sigma^-1 c).  Applies to
+ * every later call; 0 (default) = none.  EINVAL if negative or not finite. */
+exageo_status exageo_set_nugget(exageo_ctx *ctx, double tau2);
+
 /* Diagonal-super-tile (DST) approximation (paper Section 2.1, Fig. 1(b)) of
  * the likelihood calls (loglik, loglik_grad, mle; FP64 only): with the
  * locations in the library's Z-order cut into tiles of ts points, every tile
@@ -189,12 +199,13 @@ exageo_status exageo_predict(exageo_ctx *ctx, int64_t n, const double *x, const 
  * expected negative Hessian of eq. (2),
  *   I_jk = tr(Sigma^-1 dSigma_j Sigma^-1 dSigma_k) / 2,
  * computed in FP64 whatever the context's precision settings, as
- * I_jk = <B_j, B_k> / 2 with B_j = L^-1 dSigma_j L^-T (B_sigma2 = I / sigma2,
- * B_beta and B_nu by FP64 MFMA products with the regenerated derivative
- * matrices).  x, y are DEVICE pointers (n doubles, caller order); fisher is a
+ * I_jk = <B_j, B_k> / 2 with B_j = L^-1 dSigma_j L^-T (B_sigma2 = I / sigma2
+ * without a nugget; B_beta, B_nu and, with a nugget, B_sigma2 by FP64 MFMA
+ * products with the regenerated derivative matrices).  x, y are DEVICE pointers (n doubles, caller order); fisher is a
  * HOST array of 9 doubles receiving I row-major.  The library allocates
  * 3 npad^2 doubles of its own for the call (npad = n rounded up to the tile
- * size) and frees them before returning (ENOMEM if it cannot).  EINVAL while
+ * size; 4 npad^2 with a nugget, which needs B_sigma2 too) and frees them
+ * before returning (ENOMEM if it cannot).  EINVAL while
  * the DST approximation is on; ENOTPD with *info as for exageo_loglik. */
 exageo_status exageo_fisher(exageo_ctx *ctx, int64_t n, const double *x, const double *y, const double theta[3],
                             double fisher[9], int64_t *info);

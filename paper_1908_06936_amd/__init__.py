@@ -146,6 +146,11 @@ class Context:
         m = {"euclidean": _lib.EUCLIDEAN, "great_circle": _lib.GREAT_CIRCLE}[metric]
         self._check(self._lib.exageo_set_distance(self._h, m), "set_distance")
 
+    def set_nugget(self, tau2: float):
+        """Fixed nugget: tau2 added to the diagonal of Sigma in every later
+        call (0 = none)."""
+        self._check(self._lib.exageo_set_nugget(self._h, float(tau2)), "set_nugget")
+
     def set_dst_band(self, band: int):
         """DST approximation of the likelihood calls: tiles |I - J| >= band
         set to zero (0 = exact)."""

@@ -29,7 +29,7 @@ class MleStats(ctypes.Structure):
 
 EXPORTS = [
     "exageo_create", "exageo_destroy", "exageo_set_stream", "exageo_workspace_bytes", "exageo_set_workspace",
-    "exageo_set_mixed_policy", "exageo_set_mixed_fp64_band", "exageo_set_dst_band", "exageo_set_distance", "exageo_last_error",
+    "exageo_set_mixed_policy", "exageo_set_mixed_fp64_band", "exageo_set_dst_band", "exageo_set_distance", "exageo_set_nugget", "exageo_last_error",
     "exageo_matern_cov",
     "exageo_simulate", "exageo_loglik",
     "exageo_loglik_grad", "exageo_mle", "exageo_predict", "exageo_fisher", "exageo_get_timings", "exageo_set_profiling",
@@ -67,6 +67,8 @@ def load():
     lib.exageo_set_dst_band.argtypes = [p, i64]
     lib.exageo_set_distance.restype = st
     lib.exageo_set_distance.argtypes = [p, i32]
+    lib.exageo_set_nugget.restype = st
+    lib.exageo_set_nugget.argtypes = [p, d]
     lib.exageo_last_error.restype = ctypes.c_char_p
     lib.exageo_last_error.argtypes = [p]
     lib.exageo_matern_cov.restype = st

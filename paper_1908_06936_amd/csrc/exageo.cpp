@@ -107,6 +107,7 @@ struct exageo_ctx {
   double fp64_band_factor = 0.0;  // FP64 below fp64_band_factor * beta
   int64_t dst_band = 0;           // DST approximation of loglik / loglik_grad / mle (0: exact)
   int metric = EXAGEO_EUCLIDEAN;  // distance between locations
+  double nugget = 0.0;            // tau^2 added to the diagonal
   bool profiling = false;
   std::string err;
   // workspace
@@ -354,7 +355,7 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
     c->timings[12] = p.NT > 1 ? 1.0 - fbf - f64 : 0.0;
     c->timings[14] = f64;
   }
-  exg::launch_quad_table(theta, c->metric, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
+  exg::launch_quad_table(theta, c->metric, c->nugget, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   exg::launch_fill_info(at<unsigned long long>(c, p.off_info), c->stream);
   exg::launch_gen_tiles(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), at<double>(c, p.off_qt),
                         at<double>(c, p.off_cst), tag, c->stream);
@@ -618,6 +619,12 @@ exageo_status exageo_set_distance(exageo_ctx* c, int metric) {
   return EXAGEO_OK;
 }
 
+exageo_status exageo_set_nugget(exageo_ctx* c, double tau2) {
+  if (!c || !(tau2 >= 0.0) || !std::isfinite(tau2)) return EXAGEO_EINVAL;
+  c->nugget = tau2;
+  return EXAGEO_OK;
+}
+
 exageo_status exageo_set_dst_band(exageo_ctx* c, int64_t band) {
   if (!c || band < 0) return EXAGEO_EINVAL;
   c->dst_band = band;
@@ -668,7 +675,7 @@ exageo_status exageo_matern_cov(exageo_ctx* c, int64_t n, const double* x, const
   Plan p = make_plan(1, c->ts, 0);
   exageo_status st = ensure_ws(c, p);
   if (st) return st;
-  exg::launch_quad_table(theta, c->metric, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
+  exg::launch_quad_table(theta, c->metric, c->nugget, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   exg::launch_gen_dense(cov, ldc, n, x, y, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -974,7 +981,8 @@ exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const dou
   if (st) return st;
   const int64_t nparts = exg::fisher_part_blocks(p.ts, p.NT);
   const size_t full = (size_t)p.npad * (size_t)p.npad;
-  const size_t need = (3 * full + 5 * (size_t)nparts + 16) * 8;
+  const bool nug = c->nugget > 0.0;  // B_sigma2 is then not I / sigma2
+  const size_t need = ((nug ? 4 : 3) * full + 9 * (size_t)nparts + 16) * 8;
   double* buf = nullptr;
   hipError_t e = hipMalloc((void**)&buf, need);
   if (e != hipSuccess) {
@@ -989,15 +997,17 @@ exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const dou
   double* Bb = buf;                // dSigma_beta, then B_beta
   double* Mb = buf + full;         // X dSigma_j
   double* Bn = buf + 2 * full;     // dSigma_nu, then B_nu
-  double* part = buf + 3 * full;   // partial sums of the traces and products
-  double* out = part + 5 * nparts;
+  double* Bs = nug ? buf + 3 * full : nullptr;  // dSigma_sigma2, then B_sigma2
+  double* part = buf + (nug ? 4 : 3) * full;     // partial sums of the traces and products
+  double* out = part + 9 * nparts;
   const double* xs = at<double>(c, p.off_xs);
   const double* ys = at<double>(c, p.off_ys);
   const double* qt = at<double>(c, p.off_qt);
   const double* cst = at<double>(c, p.off_cst);
   exg::launch_fisher_param(M, 1, p.n, xs, ys, qt, cst, Bb, Mb, Bb, c->stream);
   exg::launch_fisher_param(M, 2, p.n, xs, ys, qt, cst, Bn, Mb, Bn, c->stream);
-  exg::launch_fisher_reduce(Bb, Bn, p.ts, p.NT, p.n, cst, part, out, c->stream);
+  if (nug) exg::launch_fisher_param(M, 0, p.n, xs, ys, qt, cst, Bs, Mb, Bs, c->stream);
+  exg::launch_fisher_reduce(Bs, Bb, Bn, p.ts, p.NT, p.n, cst, part, out, c->stream);
   rec(c, 5);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(fisher, out, 9 * 8, hipMemcpyDeviceToHost, c->stream);
@@ -1009,7 +1019,7 @@ exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const dou
     // X G (row block g runs over (g + 1) 128 columns of X) and M X^T (lower
     // block pairs (g, h), h <= g, over (h + 1) 128 columns)
     const double R = (double)((p.n + BLKH - 1) / BLKH), b3 = 2.0 * BLKH * BLKH * BLKH;
-    c->timings[18] = 2.0 * b3 * (R * R * (R + 1.0) / 2.0 + R * (R + 1.0) * (R + 2.0) / 6.0);
+    c->timings[18] = (nug ? 3.0 : 2.0) * b3 * (R * R * (R + 1.0) / 2.0 + R * (R + 1.0) * (R + 2.0) / 6.0);
   }
   const hipError_t ef = hipFree(buf);
   if (e != hipSuccess) return fail(c, EXAGEO_EDEVICE, "fisher: %s", hipGetErrorString(e));

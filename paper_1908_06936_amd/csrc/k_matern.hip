@@ -23,8 +23,8 @@ __device__ double dev_digamma(double z) {
 
 // One thread per (bucket m, node k): node t = k h_m, weights of the three
 // integrands including the trapezoidal end weight h/2 at t = 0.
-__global__ void k_quad_table(double s2, double beta, double nu, double metric, double* __restrict__ qt,
-                             double* __restrict__ cst) {
+__global__ void k_quad_table(double s2, double beta, double nu, double metric, double nugget,
+                             double* __restrict__ qt, double* __restrict__ cst) {
   const int m = blockIdx.x, k = threadIdx.x;
   const double h = 0.1 * exp2(-0.5 * m);
   const double t = k * h;
@@ -45,6 +45,7 @@ __global__ void k_quad_table(double s2, double beta, double nu, double metric, d
     cst[C_PSI] = dev_digamma(nu);
     cst[C_S2C] = s2 * c;
     cst[C_METRIC] = metric;
+    cst[C_NUG] = nugget;
   }
 }
 
@@ -137,6 +138,7 @@ __global__ __launch_bounds__(256) void k_gen_tiles(TileMat M, int T, int64_t nre
       val = (gi == gj) ? 1.0 : 0.0;
     } else {
       val = matern_value(loc_dist(xi, yi, xs[gj], ys[gj], cst), cst, qt);
+      if (gi == gj) val += cst[C_NUG];  // the observation's own noise
     }
     const int64_t e = (int64_t)c * ts;
     if (kind == 0) out64[e] = val;
@@ -153,15 +155,16 @@ __global__ __launch_bounds__(256) void k_gen_dense(double* __restrict__ cov, int
   if (i >= n) return;
   const double xi = x[i], yi = y[i];
   for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
-    cov[i + j * ldc] = matern_value(loc_dist(xi, yi, x[j], y[j], cst), cst, qt);
+    cov[i + j * ldc] = matern_value(loc_dist(xi, yi, x[j], y[j], cst), cst, qt) + (i == j ? cst[C_NUG] : 0.0);
   }
 }
 
 int64_t quad_table_doubles() { return QT_TOTAL; }
 
 // qt: QT_TOTAL doubles (quadrature nodes, then the Chebyshev tables)
-void launch_quad_table(const double theta[3], int metric, double* qt, double* cst, hipStream_t s) {
-  hipLaunchKernelGGL(k_quad_table, dim3(QNB), dim3(QNK), 0, s, theta[0], theta[1], theta[2], (double)metric, qt, cst);
+void launch_quad_table(const double theta[3], int metric, double nugget, double* qt, double* cst, hipStream_t s) {
+  hipLaunchKernelGGL(k_quad_table, dim3(QNB), dim3(QNK), 0, s, theta[0], theta[1], theta[2], (double)metric, nugget,
+                     qt, cst);
   hipLaunchKernelGGL(k_cheb_table, dim3(CH_NSEG), dim3(64), 0, s, qt, (const double*)cst);
 }
 

@@ -12,7 +12,7 @@ namespace exg {
 // k_matern.hip
 // doubles of the per-theta table array (quadrature nodes + Chebyshev tables)
 int64_t quad_table_doubles();
-void launch_quad_table(const double theta[3], int metric, double* qt, double* cst, hipStream_t s);
+void launch_quad_table(const double theta[3], int metric, double nugget, double* qt, double* cst, hipStream_t s);
 void launch_gen_tiles(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* qt,
                       const double* cst, const uint8_t* tag, hipStream_t s);
 void launch_gen_dense(double* cov, int64_t ldc, int64_t n, const double* x, const double* y, const double* qt,
@@ -90,8 +90,9 @@ void launch_krige_mse(const TileMat& M, const double* Xd, const double* xs, cons
 int64_t fisher_part_blocks(int64_t ts, int64_t NT);
 void launch_fisher_param(const TileMat& X, int comp, int64_t nreal, const double* xs, const double* ys,
                          const double* qt, const double* cst, double* G, double* Mb, double* Bs, hipStream_t s);
-// part: 5 fisher_part_blocks doubles; out: 9 doubles (device)
-void launch_fisher_reduce(const double* Bb, const double* Bn, int64_t ts, int64_t NT, int64_t nreal, const double* cst,
-                          double* part, double* out, hipStream_t s);
+// Bs: B_sigma2 or null (B_sigma2 = I / sigma2); part: 9 fisher_part_blocks
+// doubles; out: 9 doubles (device)
+void launch_fisher_reduce(const double* Bs, const double* Bb, const double* Bn, int64_t ts, int64_t NT, int64_t nreal,
+                          const double* cst, double* part, double* out, hipStream_t s);
 
 }  // namespace exg

@@ -53,7 +53,7 @@ constexpr int QT_CHEB_OFF = QNB * QNK * QW;
 constexpr int QT_TOTAL = QT_CHEB_OFF + CH_NSEG * CH_STRIDE;
 
 // per-theta constants written by the table kernel
-enum { C_S2 = 0, C_BETA, C_NU, C_C, C_PSI, C_S2C, C_METRIC, C_COUNT = 8 };
+enum { C_S2 = 0, C_BETA, C_NU, C_C, C_PSI, C_S2C, C_METRIC, C_NUG, C_COUNT = 8 };
 
 constexpr double EARTH_RADIUS_KM = 6371.0;
 
