@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a plain 1 GiB
 # device copy read and write 1 GiB.  Valid only for the kernel sources the
 # counters were taken on (fingerprint below); otherwise reported as null.
-TRAFFIC_BYTES_PER_LAUNCH = (4.9498e6 * 2.0 + 1.0333e6 * 1.0) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = (4.9520e6 * 2.0 + 1.0333e6 * 1.0) * 1024
 TRAFFIC_SOURCES = ("paper_1908_06936_amd/csrc/common.h", "paper_1908_06936_amd/csrc/k_gemm.hip")
-TRAFFIC_FINGERPRINT = "ada5aa0a89eaadf338d62f79c987f43139b9b28c"
+TRAFFIC_FINGERPRINT = "d047388d5a032c453586476b2d0f5cf4cbaa9fd3"
 
 
 def traffic_bytes():
