@@ -30,21 +30,44 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the trailing-update kernel from two rocprofv3 --pmc
 # passes over this workload (profiles/k_chol_update_n40000_ts768_counters.md):
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a plain 1 GiB
-# device copy read and write 1 GiB.  Valid only for the kernel sources the
-# counters were taken on (fingerprint below); otherwise reported as null.
+# device copy read and write 1 GiB.  Valid only for the kernel source the
+# counters were taken on: the shared GEMM core (common.h) and the text of
+# k_chol_update and of its launcher (fingerprint below); otherwise null.
 TRAFFIC_BYTES_PER_LAUNCH = (4.9520e6 * 2.0 + 1.0333e6 * 1.0) * 1024
-TRAFFIC_SOURCES = ("paper_1908_06936_amd/csrc/common.h", "paper_1908_06936_amd/csrc/k_gemm.hip")
-TRAFFIC_FINGERPRINT = "d047388d5a032c453586476b2d0f5cf4cbaa9fd3"
+TRAFFIC_FILES = ("paper_1908_06936_amd/csrc/common.h",)
+TRAFFIC_FUNCTIONS = ("paper_1908_06936_amd/csrc/k_gemm.hip", ("k_chol_update", "launch_chol_update"))
+TRAFFIC_FINGERPRINT = "45f82064a89d612e47dc11f6ab70397c72efead6"
 
 
-def traffic_bytes():
+def _function_text(src: str, name: str) -> str:
+    """Source text of the function `name` (signature to its closing brace)."""
+    i = src.index(f" {name}(")
+    j = src.index("{", i)
+    depth = 0
+    for k in range(j, len(src)):
+        depth += {"{": 1, "}": -1}.get(src[k], 0)
+        if depth == 0:
+            return src[i:k + 1]
+    raise ValueError(name)
+
+
+def traffic_fingerprint() -> str:
     import hashlib
 
     h = hashlib.sha1()
-    for f in TRAFFIC_SOURCES:
+    for f in TRAFFIC_FILES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return TRAFFIC_BYTES_PER_LAUNCH if h.hexdigest() == TRAFFIC_FINGERPRINT else None
+    path, names = TRAFFIC_FUNCTIONS
+    with open(os.path.join(ROOT, path)) as fh:
+        src = fh.read()
+    for name in names:
+        h.update(_function_text(src, name).encode())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    return TRAFFIC_BYTES_PER_LAUNCH if traffic_fingerprint() == TRAFFIC_FINGERPRINT else None
 
 
 def cpu_baseline(n_full: int, theta, sample_n: int) -> dict:
