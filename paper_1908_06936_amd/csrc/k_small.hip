@@ -157,6 +157,23 @@ __global__ void k_scatter(const double* __restrict__ v, const int32_t* __restric
 // Writes L (zeros above the diagonal) over the block, X to dinv (ld 128), the
 // block's sum of 2 ln L_jj to *ldpart and the first failing global column
 // (1-based) to *info with an atomic minimum.
+// sqrt(d) and 1 / sqrt(d) from the hardware reciprocal square root and two
+// Newton steps (each doubles the correct bits: y <- y + y (1 - d y^2) / 2),
+// then one Newton step on the square root itself (s <- s + (d - s^2) / (2 s));
+// within an ulp or two of the correctly rounded values, without the long
+// correctly rounded sequences on the factorisation's serial path.
+__device__ __forceinline__ void sqrt_and_rsqrt(double d, double* sq, double* rsq) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  const double s0 = d * y;
+  *sq = fma(0.5 * y, fma(-s0, s0, d), s0);
+  *rsq = y;
+}
+
 __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64_t lda, double* __restrict__ dinv,
                                                    double* __restrict__ ldpart, unsigned long long* __restrict__ info,
                                                    int64_t col0) {
@@ -165,7 +182,8 @@ __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64
   // block and the lookahead panel is not starved by the update.
   __shared__ double Ls[BLK * (BLK + 1) / 2];
   __shared__ double pub[2][BLK];  // published column (factor) / row (inverse)
-  __shared__ double dg[BLK];
+  __shared__ double dg[BLK];      // L_jj
+  __shared__ double idg[BLK];     // 1 / L_jj
   const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
   double a[8][8];
 #pragma unroll
@@ -192,10 +210,11 @@ __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64
       }
       __syncthreads();
       const double d = pub[buf][j];
-      const double sd = sqrt(d);
-      const double isd = 1.0 / sd;
+      double sd, isd;
+      sqrt_and_rsqrt(d, &sd, &isd);
       if (t == 0) {
         dg[j] = sd;
+        idg[j] = isd;
         if (!(d > 0.0) || !(d <= DBL_MAX)) atomicMin(info, (unsigned long long)(col0 + j + 1));
       }
       const double id = isd * isd;
@@ -253,7 +272,7 @@ __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64
         if (tc == 0) pub[buf][m] = 1.0;
       }
       __syncthreads();
-      const double inv_lmm = 1.0 / dg[m];
+      const double inv_lmm = idg[m];
       double li[8], tm[8];
 #pragma unroll
       for (int p = pm; p < 8; ++p) {
@@ -276,14 +295,15 @@ __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int r = tr + 16 * p, c = tc + 16 * q;
-      const double il = 1.0 / dg[r];
+      const double il = idg[r];
       dinv[r + c * BLK] = (r > c) ? a[p][q] * il : ((r == c) ? il : 0.0);
     }
-  if (t == 0) {
-    double s = 0.0;
-    for (int j = 0; j < BLK; ++j) s += 2.0 * log(dg[j]);
-    *ldpart = s;
-  }
+  // 2 sum ln L_jj: one logarithm per thread, fixed-order block sum (pub is
+  // free once every thread has left the inverse loop)
+  __syncthreads();
+  double lg[1] = {t < BLK ? 2.0 * log(dg[t]) : 0.0};
+  block_sum<1>(lg, &pub[0][0]);
+  if (t == 0) *ldpart = lg[0];
 }
 
 // ------------------------------------------------------- triangular solves
