@@ -74,7 +74,8 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
   }
   p.off_xd = take((size_t)p.NT * tt * 8);
   // FP64 inverse: FP64 staging buffer (the mixed inverse stages in the FP32 panel copy)
-  p.off_ptmp = p.grad && !p.mixed ? take((size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8) : 0;
+  // (two halves: consecutive TRTRI steps stage on different streams)
+  p.off_ptmp = p.grad && !p.mixed ? take(2 * (size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8) : 0;
   p.off_dinv = take((size_t)p.NT * p.T * BLKH * BLKH * 8);
   p.off_ld = take((size_t)p.NT * p.T * 8);
   p.off_xs = take((size_t)p.npad * 8);
@@ -486,9 +487,28 @@ exageo_status gradient(exageo_ctx* c, const Plan& p) {
                                            at<double>(c, p.off_part), c->stream);
   } else {
     exg::launch_trsv_bwd(M, Xd, rhs, av, c->stream);
-    // L^-1 in place, then the fused LAUUM + contraction
-    for (int64_t k = 0; k < p.NT; ++k)
-      exg::launch_trtri_step(M, Xd + k * p.ts * p.ts, at<double>(c, p.off_ptmp), k, p.n, c->stream);
+    // L^-1 in place, then the fused LAUUM + contraction.  Step k + 1's first
+    // half runs on the side stream beside step k's second half, staging in the
+    // other half of the buffer: ev_col = "first half of the next step done",
+    // ev_panel = "the main stream has finished every step before this one".
+    const int64_t tt = p.ts * p.ts, half = std::max<int64_t>(1, p.NT - 1) * tt;
+    double* P2 = at<double>(c, p.off_ptmp);
+    hipStream_t S = c->stream, S2 = c->side;
+    HIPCHK(c, hipEventRecord(c->ev_panel, S));
+    HIPCHK(c, hipStreamWaitEvent(S2, c->ev_panel, 0));
+    exg::launch_trtri_right(M, Xd, P2, 0, p.n, S2);
+    HIPCHK(c, hipEventRecord(c->ev_col, S2));
+    for (int64_t k = 0; k < p.NT; ++k) {
+      double* Pk = P2 + (k & 1) * half;
+      HIPCHK(c, hipStreamWaitEvent(S, c->ev_col, 0));
+      if (k + 1 < p.NT) {
+        HIPCHK(c, hipEventRecord(c->ev_panel, S));
+        HIPCHK(c, hipStreamWaitEvent(S2, c->ev_panel, 0));
+        exg::launch_trtri_right(M, Xd + (k + 1) * tt, P2 + ((k + 1) & 1) * half, k + 1, p.n, S2);
+        HIPCHK(c, hipEventRecord(c->ev_col, S2));
+      }
+      exg::launch_trtri_rest(M, Xd + k * tt, Pk, k, p.n, S);
+    }
     exg::launch_lauum_contract(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
                                at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part),
                                c->stream);

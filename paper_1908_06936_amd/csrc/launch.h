@@ -74,6 +74,9 @@ void launch_panel(double* Dk, double* below, int64_t ts, int64_t NT, int64_t k, 
                   double* ldpart_k, unsigned long long* info, hipStream_t s);
 void launch_diag_inverses(double* Xd, const double* diag, const double* dinv, int64_t ts, int64_t NT, hipStream_t s);
 void launch_trtri_step(const TileMat& M, const double* Xk, double* P, int64_t k, int64_t nreal, hipStream_t s);
+// the step's two halves: P_k and column k (any stream), then the rest
+void launch_trtri_right(const TileMat& M, const double* Xk, double* P, int64_t k, int64_t nreal, hipStream_t s);
+void launch_trtri_rest(const TileMat& M, const double* Xk, double* P, int64_t k, int64_t nreal, hipStream_t s);
 int64_t lauum_blocks(int64_t ts, int64_t NT);
 void launch_lauum_contract(const TileMat& M, int64_t nreal, const double* xs, const double* ys, const double* av,
                            const double* qt, const double* cst, double* part, hipStream_t s);
