@@ -144,19 +144,6 @@ __global__ void k_scatter(const double* __restrict__ v, const int32_t* __restric
   if (i < n) out[perm[i]] = v[i];
 }
 
-// ------------------------------------------------ diagonal 128-block factor
-// Cholesky of one 128 x 128 block and the inverse of its factor.
-// 256 threads; thread (tr, tc) = (t % 16, t / 16) holds the 64 entries
-// (tr + 16 p, tc + 16 q) in registers.
-//   factor (right-looking, one barrier per column): the owners of column j
-//   publish it to LDS, then every thread applies A_rc -= A_rj A_cj / A_jj to
-//   its entries with r, c > j and the owners keep L_rj = A_rj / sqrt(A_jj).
-//   inverse: L goes to LDS; with T = unit lower triangular, rows m = 0..127:
-//   the owners of row m publish it and T_ij -= (L_im / L_mm) T_mj for i > m >= j;
-//   then X = L^-1 has X_ij = T_ij / L_ii.
-// Writes L (zeros above the diagonal) over the block, X to dinv (ld 128), the
-// block's sum of 2 ln L_jj to *ldpart and the first failing global column
-// (1-based) to *info with an atomic minimum.
 // sqrt(d) and 1 / sqrt(d) from the hardware reciprocal square root and two
 // Newton steps (each doubles the correct bits: y <- y + y (1 - d y^2) / 2),
 // then one Newton step on the square root itself (s <- s + (d - s^2) / (2 s));
@@ -174,6 +161,19 @@ __device__ __forceinline__ void sqrt_and_rsqrt(double d, double* sq, double* rsq
   *rsq = y;
 }
 
+// ------------------------------------------------ diagonal 128-block factor
+// Cholesky of one 128 x 128 block and the inverse of its factor.
+// 256 threads; thread (tr, tc) = (t % 16, t / 16) holds the 64 entries
+// (tr + 16 p, tc + 16 q) in registers.
+//   factor (right-looking, one barrier per column): the owners of column j
+//   publish it to LDS, then every thread applies A_rc -= A_rj A_cj / A_jj to
+//   its entries with r, c > j and the owners keep L_rj = A_rj / sqrt(A_jj).
+//   inverse: L goes to LDS; with T = unit lower triangular, rows m = 0..127:
+//   the owners of row m publish it and T_ij -= (L_im / L_mm) T_mj for i > m >= j;
+//   then X = L^-1 has X_ij = T_ij / L_ii.
+// Writes L (zeros above the diagonal) over the block, X to dinv (ld 128), the
+// block's sum of 2 ln L_jj to *ldpart and the first failing global column
+// (1-based) to *info with an atomic minimum.
 __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64_t lda, double* __restrict__ dinv,
                                                    double* __restrict__ ldpart, unsigned long long* __restrict__ info,
                                                    int64_t col0) {
@@ -231,8 +231,9 @@ __global__ __launch_bounds__(256) void k_potrf_blk(double* __restrict__ A, int64
       }
 #pragma unroll
       for (int q = qj; q < 8; ++q) {
+        // lower blocks only: the upper ones are never read
 #pragma unroll
-        for (int p = qj; p < 8; ++p) a[p][q] -= lr[p] * lc[q];
+        for (int p = q; p < 8; ++p) a[p][q] -= lr[p] * lc[q];
       }
       if (tc == jj) {
 #pragma unroll
