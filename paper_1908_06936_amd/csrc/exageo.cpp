@@ -467,48 +467,64 @@ exageo_status solve_reduce(exageo_ctx* c, const Plan& p) {
   return EXAGEO_OK;
 }
 
+// X = L^-1 in place: step k + 1's first half (P = -L_ik X_kk into the other
+// staging half, column k + 1 written back) runs on the side stream beside
+// step k's second half on the main stream.  ev_col = "first half of the next
+// step done"; ev_panel = "the main stream has finished every earlier step".
+template <class Right, class Rest>
+exageo_status trtri_two_streams(exageo_ctx* c, int64_t NT, Right right, Rest rest) {
+  hipStream_t S = c->stream, S2 = c->side;
+  HIPCHK(c, hipEventRecord(c->ev_panel, S));
+  HIPCHK(c, hipStreamWaitEvent(S2, c->ev_panel, 0));
+  right(0, S2);
+  HIPCHK(c, hipEventRecord(c->ev_col, S2));
+  for (int64_t k = 0; k < NT; ++k) {
+    HIPCHK(c, hipStreamWaitEvent(S, c->ev_col, 0));
+    if (k + 1 < NT) {
+      HIPCHK(c, hipEventRecord(c->ev_panel, S));
+      HIPCHK(c, hipStreamWaitEvent(S2, c->ev_panel, 0));
+      right(k + 1, S2);
+      HIPCHK(c, hipEventRecord(c->ev_col, S2));
+    }
+    rest(k, S);
+  }
+  return EXAGEO_OK;
+}
+
 exageo_status gradient(exageo_ctx* c, const Plan& p) {
   const exg::TileMat M = tilemat(c, p);
   double* rhs = at<double>(c, p.off_av);
   double* av = at<double>(c, p.off_alpha);
   double* Xd = at<double>(c, p.off_xd);
   int64_t nparts = exg::lauum_blocks(p.ts, p.NT);  // partial triples of the contraction
+  const int64_t tt = p.ts * p.ts, half = std::max<int64_t>(1, p.NT - 1) * tt;
   // a = Sigma^-1 z = L^-T y
   exg::launch_copy(rhs, at<double>(c, p.off_y), p.npad, c->stream);
+  exageo_status st;
   if (p.mixed) {
     // mixed precision: the same steps with FP32 off-diagonal tiles of L^-1
+    // (staged in the two halves of the FP32 panel copy)
     const uint8_t* tag = at<uint8_t>(c, p.off_tag);
+    float* P32 = at<float>(c, p.off_p32);
     exg::launch_trsv_bwd_lp(M, tag, Xd, rhs, av, c->stream);
-    for (int64_t k = 0; k < p.NT; ++k)
-      exg::launch_trtri_step_lp(M, tag, Xd + k * p.ts * p.ts, at<float>(c, p.off_p32), k, p.n, c->stream);
+    st = trtri_two_streams(
+        c, p.NT,
+        [&](int64_t k, hipStream_t s) { exg::launch_trtri_right_lp(M, tag, Xd + k * tt, P32 + (k & 1) * half, k, p.n, s); },
+        [&](int64_t k, hipStream_t s) { exg::launch_trtri_rest_lp(M, Xd + k * tt, P32 + (k & 1) * half, k, p.n, s); });
+    if (st) return st;
     nparts = exg::launch_lauum_contract_lp(M, tag, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
                                            at<double>(c, p.off_qt), at<double>(c, p.off_cst),
                                            at<int32_t>(c, p.off_bli), at<int32_t>(c, p.off_blj), c->bfirst[p.NT],
                                            at<double>(c, p.off_part), c->stream);
   } else {
     exg::launch_trsv_bwd(M, Xd, rhs, av, c->stream);
-    // L^-1 in place, then the fused LAUUM + contraction.  Step k + 1's first
-    // half runs on the side stream beside step k's second half, staging in the
-    // other half of the buffer: ev_col = "first half of the next step done",
-    // ev_panel = "the main stream has finished every step before this one".
-    const int64_t tt = p.ts * p.ts, half = std::max<int64_t>(1, p.NT - 1) * tt;
-    double* P2 = at<double>(c, p.off_ptmp);
-    hipStream_t S = c->stream, S2 = c->side;
-    HIPCHK(c, hipEventRecord(c->ev_panel, S));
-    HIPCHK(c, hipStreamWaitEvent(S2, c->ev_panel, 0));
-    exg::launch_trtri_right(M, Xd, P2, 0, p.n, S2);
-    HIPCHK(c, hipEventRecord(c->ev_col, S2));
-    for (int64_t k = 0; k < p.NT; ++k) {
-      double* Pk = P2 + (k & 1) * half;
-      HIPCHK(c, hipStreamWaitEvent(S, c->ev_col, 0));
-      if (k + 1 < p.NT) {
-        HIPCHK(c, hipEventRecord(c->ev_panel, S));
-        HIPCHK(c, hipStreamWaitEvent(S2, c->ev_panel, 0));
-        exg::launch_trtri_right(M, Xd + (k + 1) * tt, P2 + ((k + 1) & 1) * half, k + 1, p.n, S2);
-        HIPCHK(c, hipEventRecord(c->ev_col, S2));
-      }
-      exg::launch_trtri_rest(M, Xd + k * tt, Pk, k, p.n, S);
-    }
+    // L^-1 in place, then the fused LAUUM + contraction
+    double* P64 = at<double>(c, p.off_ptmp);
+    st = trtri_two_streams(
+        c, p.NT,
+        [&](int64_t k, hipStream_t s) { exg::launch_trtri_right(M, Xd + k * tt, P64 + (k & 1) * half, k, p.n, s); },
+        [&](int64_t k, hipStream_t s) { exg::launch_trtri_rest(M, Xd + k * tt, P64 + (k & 1) * half, k, p.n, s); });
+    if (st) return st;
     exg::launch_lauum_contract(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
                                at<double>(c, p.off_qt), at<double>(c, p.off_cst), at<double>(c, p.off_part),
                                c->stream);

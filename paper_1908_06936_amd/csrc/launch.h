@@ -55,6 +55,9 @@ void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, 
 // one step of the mixed inverse (FP32 off-diagonal tiles of L^-1, FP32 buffer P)
 void launch_trtri_step_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k, int64_t nreal,
                           hipStream_t s);
+void launch_trtri_right_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k,
+                           int64_t nreal, hipStream_t s);
+void launch_trtri_rest_lp(const TileMat& M, const double* Xk, float* P, int64_t k, int64_t nreal, hipStream_t s);
 // mixed fused LAUUM + contraction; returns the number of partial triples
 int64_t launch_lauum_contract_lp(const TileMat& M, const uint8_t* tag, int64_t nreal, const double* xs,
                                  const double* ys, const double* av, const double* qt, const double* cst,
