@@ -1028,8 +1028,18 @@ exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const dou
   const exg::TileMat M = tilemat(c, p);
   double* Xd = at<double>(c, p.off_xd);
   // L^-1 in place (the tile matrix then holds X = L^-1, lower-triangular tiles)
-  for (int64_t k = 0; k < p.NT; ++k)
-    exg::launch_trtri_step(M, Xd + k * p.ts * p.ts, at<double>(c, p.off_ptmp), k, p.n, c->stream);
+  {
+    const int64_t tt = p.ts * p.ts, half = std::max<int64_t>(1, p.NT - 1) * tt;
+    double* P64 = at<double>(c, p.off_ptmp);
+    st = trtri_two_streams(
+        c, p.NT,
+        [&](int64_t k, hipStream_t s) { exg::launch_trtri_right(M, Xd + k * tt, P64 + (k & 1) * half, k, p.n, s); },
+        [&](int64_t k, hipStream_t s) { exg::launch_trtri_rest(M, Xd + k * tt, P64 + (k & 1) * half, k, p.n, s); });
+    if (st) {
+      (void)hipFree(buf);
+      return st;
+    }
+  }
   double* Bb = buf;                // dSigma_beta, then B_beta
   double* Mb = buf + full;         // X dSigma_j
   double* Bn = buf + 2 * full;     // dSigma_nu, then B_nu

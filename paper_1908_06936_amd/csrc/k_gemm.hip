@@ -369,32 +369,12 @@ void launch_diag_inverses(double* Xd, const double* diag, const double* dinv, in
   }
 }
 
-void launch_trtri_step(const TileMat& M, const double* Xk, double* P, int64_t k, int64_t nreal, hipStream_t s) {
-  const int64_t ts = M.ts, NT = M.NT;
-  const int T = (int)(ts / BLK);
-  const int64_t tt = ts * ts;
-  const int64_t nbelow = NT - k - 1;
-  if (nbelow > 0) {
-    const int64_t nr = nbelow * T * T, ng = nbelow * k * T * T;
-    hipLaunchKernelGGL(k_tri_right, dim3((unsigned)nr), dim3(256), 0, s, M, Xk, P, T, k, nreal, nr);
-    if (k > 0) hipLaunchKernelGGL(k_tri_gemm, dim3((unsigned)ng), dim3(256), 0, s, M, P, T, k, nreal, ng);
-    hipLaunchKernelGGL(k_copy_back, dim3((unsigned)((nbelow * tt + 255) / 256)), dim3(256), 0, s, M, P, nbelow, k + 1,
-                       k, 1);
-  }
-  if (k > 0) {
-    const int64_t nl = k * T * T;
-    hipLaunchKernelGGL(k_tri_left, dim3((unsigned)nl), dim3(256), 0, s, M, Xk, P, T, k, nl);
-    hipLaunchKernelGGL(k_copy_back, dim3((unsigned)((k * tt + 255) / 256)), dim3(256), 0, s, M, P, k, k, (int64_t)0,
-                       0);
-  }
-  launch_copy(M.diag + k * tt, Xk, tt, s);
-}
-
-// The same step in two halves for two streams.  The first half (P_i = -A_ik
+// Step k of the in-place tile inverse X = L^-1 (after this step rows 0..k of
+// X are final), in two halves for two streams.  The first half (P_i = -A_ik
 // X_kk into P, then column k <- P) reads only column k of L and X_kk, which no
 // earlier step writes, so step k + 1's first half can run beside step k's
-// second half (the update of the tiles left of column k and row k) when the
-// two use different staging buffers.
+// second half (A_ij += P_i A_kj left of column k, row k <- X_kk A_kj, the
+// diagonal tile <- X_kk) when the two use different staging buffers.
 void launch_trtri_right(const TileMat& M, const double* Xk, double* P, int64_t k, int64_t nreal, hipStream_t s) {
   const int64_t ts = M.ts, NT = M.NT;
   const int T = (int)(ts / BLK);

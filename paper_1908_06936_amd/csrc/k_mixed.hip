@@ -536,28 +536,6 @@ void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, 
   }
 }
 
-void launch_trtri_step_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k, int64_t nreal,
-                          hipStream_t s) {
-  const int64_t ts = M.ts, NT = M.NT;
-  const int T = (int)(ts / BLK);
-  const int64_t tt = ts * ts;
-  const int64_t nbelow = NT - k - 1;
-  if (nbelow > 0) {
-    const int64_t nr = nbelow * T * T, ng = nbelow * k * T * T;
-    hipLaunchKernelGGL(k_tri_right_lp, dim3((unsigned)nr), dim3(256), 0, s, M, tag, Xk, P, T, k, nreal, nr);
-    if (k > 0) hipLaunchKernelGGL(k_tri_gemm_lp, dim3((unsigned)ng), dim3(256), 0, s, M, P, T, k, nreal, ng);
-    hipLaunchKernelGGL(k_copy_back_lp, dim3((unsigned)((nbelow * tt + 255) / 256)), dim3(256), 0, s, M, P, nbelow,
-                       k + 1, k, 1);
-  }
-  if (k > 0) {
-    const int64_t nl = k * T * T;
-    hipLaunchKernelGGL(k_tri_left_lp, dim3((unsigned)nl), dim3(256), 0, s, M, Xk, P, T, k, nl);
-    hipLaunchKernelGGL(k_copy_back_lp, dim3((unsigned)((k * tt + 255) / 256)), dim3(256), 0, s, M, P, k, k,
-                       (int64_t)0, 0);
-  }
-  launch_copy(M.diag + k * tt, Xk, tt, s);
-}
-
 // the step's two halves for two streams, as launch_trtri_right / _rest
 void launch_trtri_right_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k,
                            int64_t nreal, hipStream_t s) {

@@ -53,8 +53,6 @@ void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, co
 void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, double* rhs, double* a,
                         hipStream_t s);
 // one step of the mixed inverse (FP32 off-diagonal tiles of L^-1, FP32 buffer P)
-void launch_trtri_step_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k, int64_t nreal,
-                          hipStream_t s);
 void launch_trtri_right_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k,
                            int64_t nreal, hipStream_t s);
 void launch_trtri_rest_lp(const TileMat& M, const double* Xk, float* P, int64_t k, int64_t nreal, hipStream_t s);
@@ -76,7 +74,6 @@ void launch_band_update(const TileMat& M, const double* below, int64_t k, int64_
 void launch_panel(double* Dk, double* below, int64_t ts, int64_t NT, int64_t k, int64_t nreal, double* dinv_k,
                   double* ldpart_k, unsigned long long* info, hipStream_t s);
 void launch_diag_inverses(double* Xd, const double* diag, const double* dinv, int64_t ts, int64_t NT, hipStream_t s);
-void launch_trtri_step(const TileMat& M, const double* Xk, double* P, int64_t k, int64_t nreal, hipStream_t s);
 // the step's two halves: P_k and column k (any stream), then the rest
 void launch_trtri_right(const TileMat& M, const double* Xk, double* P, int64_t k, int64_t nreal, hipStream_t s);
 void launch_trtri_rest(const TileMat& M, const double* Xk, double* P, int64_t k, int64_t nreal, hipStream_t s);
