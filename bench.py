@@ -207,6 +207,50 @@ def mle_study(args) -> int:
     return 0
 
 
+def mle_large(args) -> int:
+    """One estimator on an m x m jittered grid (default 300 x 300, n = 90,000),
+    true theta = (1, beta, 0.5), start (0.5, 0.3, 0.5), tile 768 (one JSON
+    line; progress lines on stderr, one per evaluation).  Estimators:
+    fp64_lbfgsb, fp64_dfo, mixed_dfo, mixed_lbfgsb_fp64_finish; mixed policy
+    --mle-policy: fp32 (FP32 off-diagonal tiles) or bf16_3beta (BF16 beyond
+    3 beta).  theta-hat and l(theta-hat) re-evaluated in FP64 are reported so
+    that runs of different estimators compare directly."""
+    import torch
+
+    import inputgen
+    import paper_1908_06936_amd as exa
+
+    dev = torch.device("cuda:0")
+    m, beta = args.big_n_side, args.mle_beta
+    x, y = inputgen.jittered_grid(m, seed=0)
+    e = inputgen.normals(x.size, seed=0)
+    X, Y, E = (torch.as_tensor(a, device=dev) for a in (x, y, e))
+    ctx = exa.Context(ts=768)
+    th_true = [1.0, beta, 0.5]
+    Z = ctx.simulate(X, Y, th_true, E)
+    torch.cuda.synchronize()
+    lb, ub, th0 = [0.01, 0.001, 0.1], [5.0, 2.0, 3.0], [0.5, 0.3, 0.5]
+    meth, prec = {"fp64_lbfgsb": ("lbfgsb", "fp64"), "fp64_dfo": ("dfo", "fp64"), "mixed_dfo": ("dfo", "mixed"),
+                  "mixed_lbfgsb_fp64_finish": ("lbfgsb_fp64_finish", "mixed")}[args.mle_estimator]
+    ctx.set_mixed_policy(3.0 if args.mle_policy == "bf16_3beta" else 0.0)
+    ctx.set_verbose(True)
+    print(f"[mle-large] n={x.size} beta={beta} {args.mle_estimator} policy={args.mle_policy} cap={args.mle_cap}",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    th_hat, l_hat, st = ctx.mle(X, Y, Z, lb, ub, theta0=th0, tol=1e-4, max_iters=args.mle_cap, method=meth,
+                                precision=prec)
+    wall = time.perf_counter() - t0
+    ctx.set_verbose(False)
+    l64 = ctx.loglik_status(X, Y, Z, th_hat, "fp64")[1]
+    out = {"study": "mle_large", "n": int(x.size), "grid": f"{m}x{m} jittered, seed 0", "data": "synthetic",
+           "theta_true": th_true, "theta0": th0, "lb": lb, "ub": ub, "estimator": args.mle_estimator,
+           "mixed_policy": args.mle_policy if prec == "mixed" else None, "max_evals": args.mle_cap,
+           "theta_hat": th_hat, "loglik_reported": l_hat, "loglik_fp64_at_theta_hat": l64, "wall_s": wall,
+           "stats": st}
+    print(json.dumps(out))
+    return 0
+
+
 def precision_study(args) -> int:
     """l in FP64 and in mixed precision at n = 90,000 (300 x 300 jittered grid,
     theta = (1, beta, 0.5), beta in {0.03, 0.1}, tile 768): relative
@@ -270,6 +314,13 @@ def main() -> int:
                     help="grid side of the large single evaluations (0: skip them)")
     ap.add_argument("--mle-all", action="store_true", help="also the plain mixed-precision estimators")
     ap.add_argument("--mle-nus", type=float, nargs="+", default=[0.5, 0.8], help="true nu of the n = 40,000 fields")
+    ap.add_argument("--mle-large", action="store_true",
+                    help="instead of the throughput step: one estimator on the --big-n-side grid (see mle_large)")
+    ap.add_argument("--mle-beta", type=float, default=0.03)
+    ap.add_argument("--mle-estimator", default="fp64_lbfgsb",
+                    choices=["fp64_lbfgsb", "fp64_dfo", "mixed_dfo", "mixed_lbfgsb_fp64_finish"])
+    ap.add_argument("--mle-policy", default="bf16_3beta", choices=["fp32", "bf16_3beta"])
+    ap.add_argument("--mle-cap", type=int, default=60, help="evaluation cap of --mle-large")
     ap.add_argument("--precision-study", action="store_true",
                     help="instead of the throughput step: FP64 vs mixed-precision l on a 300 x 300 jittered grid")
     args = ap.parse_args()
@@ -289,6 +340,10 @@ def main() -> int:
         return mle_study(args)
     if args.precision_study:
         return precision_study(args)
+    if args.mle_large:
+        if args.big_n_side == 400 and "--big-n-side" not in sys.argv:
+            args.big_n_side = 300
+        return mle_large(args)
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "

@@ -245,6 +245,11 @@ exageo_status exageo_mle(exageo_ctx *ctx, int64_t n, const double *x, const doub
 int exageo_get_timings(const exageo_ctx *ctx, double *out, int nmax);
 exageo_status exageo_set_profiling(exageo_ctx *ctx, int on);
 
+/* Progress of exageo_mle: with on != 0 every objective evaluation prints one
+ * line to stderr (evaluation count, precision, theta, l or the failure) and
+ * flushes it, so that long estimations show their progress.  Default off. */
+exageo_status exageo_set_verbose(exageo_ctx *ctx, int on);
+
 #ifdef __cplusplus
 }
 #endif

@@ -146,6 +146,10 @@ class Context:
         m = {"euclidean": _lib.EUCLIDEAN, "great_circle": _lib.GREAT_CIRCLE}[metric]
         self._check(self._lib.exageo_set_distance(self._h, m), "set_distance")
 
+    def set_verbose(self, on: bool = True):
+        """MLE progress: one line per objective evaluation on stderr."""
+        self._check(self._lib.exageo_set_verbose(self._h, int(on)), "set_verbose")
+
     def set_nugget(self, tau2: float):
         """Fixed nugget: tau2 added to the diagonal of Sigma in every later
         call (0 = none)."""

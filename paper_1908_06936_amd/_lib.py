@@ -29,7 +29,7 @@ class MleStats(ctypes.Structure):
 
 EXPORTS = [
     "exageo_create", "exageo_destroy", "exageo_set_stream", "exageo_workspace_bytes", "exageo_set_workspace",
-    "exageo_set_mixed_policy", "exageo_set_mixed_fp64_band", "exageo_set_dst_band", "exageo_set_distance", "exageo_set_nugget", "exageo_last_error",
+    "exageo_set_mixed_policy", "exageo_set_mixed_fp64_band", "exageo_set_dst_band", "exageo_set_distance", "exageo_set_nugget", "exageo_set_verbose", "exageo_last_error",
     "exageo_matern_cov",
     "exageo_simulate", "exageo_loglik",
     "exageo_loglik_grad", "exageo_mle", "exageo_predict", "exageo_fisher", "exageo_get_timings", "exageo_set_profiling",
@@ -69,6 +69,8 @@ def load():
     lib.exageo_set_distance.argtypes = [p, i32]
     lib.exageo_set_nugget.restype = st
     lib.exageo_set_nugget.argtypes = [p, d]
+    lib.exageo_set_verbose.restype = st
+    lib.exageo_set_verbose.argtypes = [p, i32]
     lib.exageo_last_error.restype = ctypes.c_char_p
     lib.exageo_last_error.argtypes = [p]
     lib.exageo_matern_cov.restype = st

@@ -109,6 +109,7 @@ struct exageo_ctx {
   int64_t dst_band = 0;           // DST approximation of loglik / loglik_grad / mle (0: exact)
   int metric = EXAGEO_EUCLIDEAN;  // distance between locations
   double nugget = 0.0;            // tau^2 added to the diagonal
+  bool verbose = false;           // exageo_mle prints one line per evaluation
   bool profiling = false;
   std::string err;
   // workspace
@@ -655,6 +656,12 @@ exageo_status exageo_set_distance(exageo_ctx* c, int metric) {
   return EXAGEO_OK;
 }
 
+exageo_status exageo_set_verbose(exageo_ctx* c, int on) {
+  if (!c) return EXAGEO_EINVAL;
+  c->verbose = on != 0;
+  return EXAGEO_OK;
+}
+
 exageo_status exageo_set_nugget(exageo_ctx* c, double tau2) {
   if (!c || !(tau2 >= 0.0) || !std::isfinite(tau2)) return EXAGEO_EINVAL;
   c->nugget = tau2;
@@ -870,6 +877,12 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
     checked_box = true;
     if (g) ++ngev;
     else ++nev;
+    if (c->verbose) {
+      std::fprintf(stderr, "[exageo_mle] eval %lld %s%s theta = (%.10g, %.10g, %.10g) l = %.12g%s\n",
+                   (long long)(nev + ngev), cur->mixed ? "mixed" : "fp64", g ? " +grad" : "", th[0], th[1], th[2],
+                   ll, s == EXAGEO_OK ? "" : " (failed)");
+      std::fflush(stderr);
+    }
     if (s == EXAGEO_OK) {
       *f = ll;
       return true;
