@@ -84,7 +84,7 @@ def test_matern_cov_across_interpolation_segments(orc, ctx256, nu):
 # ------------------------------------------------------------ likelihood
 @pytest.mark.parametrize("n,ts,nu", [(1, 256, 0.5), (7, 128, 1.0), (300, 128, 0.5), (1000, 256, 1.0),
                                      (1500, 128, 1.7), (2100, 512, 0.8), (256, 256, 1.0), (257, 256, 0.5),
-                                     (2500, 1024, 1.0)])
+                                     (2500, 1024, 1.0), (2500, 2048, 0.7)])
 def test_loglik_vs_oracle(orc, exa, n, ts, nu):
     ctx = exa.Context(ts=ts)
     x, y = inputgen.uniform(n, seed=n)
@@ -182,9 +182,9 @@ def test_loglik_permutation_and_determinism(orc, ctx256):
 @pytest.mark.parametrize("n,ts,th", [(700, 256, [1.0, 0.1, 1.0]), (1200, 128, [1.4, 0.05, 0.6]),
                                      (500, 512, [0.9, 0.2, 2.2]), (1, 128, [1.3, 0.1, 0.5]),
                                      (256, 128, [1.0, 0.1, 0.8]), (129, 128, [0.7, 0.08, 1.1]),
-                                     (2500, 1024, [1.0, 0.1, 1.0])])
+                                     (2500, 1024, [1.0, 0.1, 1.0]), (2500, 2048, [1.1, 0.08, 0.9])])
 def test_grad_vs_oracle(orc, exa, n, ts, th):
-    # one point, whole tiles, one real row in the last tile, tile 1024
+    # one point, whole tiles, one real row in the last tile, tiles 1024 and 2048
     ctx = exa.Context(ts=ts)
     x, y = inputgen.uniform(n, seed=n + 1)
     z = orc.simulate(x, y, th, inputgen.normals(n, seed=n + 1)) if n > 1 else np.array([0.6])
