@@ -139,7 +139,7 @@ def mle_study(args) -> int:
     # (nu = 0.8) field; evaluation caps keep each run within a few minutes
     lb, ub, th0 = [0.01, 0.01, 0.1], [5.0, 2.0, 3.0], [0.5, 0.3, 0.5]
     out["n40000_grid"] = {}
-    for th_true in [[1.0, 0.1, nu] for nu in args.mle_nus]:
+    for th_true in [[1.0, 0.1, nu] for nu in (args.mle_nus if not args.mle_skip_40k else [])]:
         ctx, X, Y, Z = field(200, th_true, 1, 768)
         runs = {}
         estimators = [("fp64_dfo", "dfo", "fp64", 400), ("fp64_lbfgsb", "lbfgsb", "fp64", 80),
@@ -314,6 +314,7 @@ def main() -> int:
                     help="grid side of the large single evaluations (0: skip them)")
     ap.add_argument("--mle-all", action="store_true", help="also the plain mixed-precision estimators")
     ap.add_argument("--mle-nus", type=float, nargs="+", default=[0.5, 0.8], help="true nu of the n = 40,000 fields")
+    ap.add_argument("--mle-skip-40k", action="store_true", help="--mle-study without the n = 40,000 estimators")
     ap.add_argument("--mle-large", action="store_true",
                     help="instead of the throughput step: one estimator on the --big-n-side grid (see mle_large)")
     ap.add_argument("--mle-beta", type=float, default=0.03)

@@ -304,3 +304,17 @@ def test_mle_config1(orc, ctx768, method):
     assert orc.loglik(x, y, z, th) == pytest.approx(ll, rel=1e-10)
     assert ll >= ll_o - 1e-3
     assert stats["status"] == "OK"
+
+
+def test_mle_progress_lines(capfd, ctx768):
+    x, y = inputgen.jittered_grid(12, seed=3)
+    z = inputgen.normals(x.size, seed=3)
+    ctx768.set_verbose(True)
+    try:
+        _, _, stats = ctx768.mle(dev(x), dev(y), dev(z), [0.01] * 3, [5.0] * 3, theta0=[1.0, 0.1, 0.5],
+                                 max_iters=5, method="lbfgsb")
+    finally:
+        ctx768.set_verbose(False)
+    err = capfd.readouterr().err
+    lines = [s for s in err.splitlines() if s.startswith("[exageo_mle] eval")]
+    assert len(lines) == stats["n_grad_evals"] + stats["n_evals"] and "fp64 +grad" in lines[0]
