@@ -436,11 +436,6 @@ __global__ __launch_bounds__(256) void k_finalize_grad(const double* __restrict_
 // ------------------------------------------------------------ fills/copies
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v) { *p = v; }
 
-__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 __global__ void k_copy_f64(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -543,10 +538,6 @@ void launch_finalize_grad(const double* part, int64_t nparts, double* out, hipSt
 
 void launch_fill_info(unsigned long long* info, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, info, ~0ull);
-}
-
-void launch_fill(double* p, int64_t n, double v, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3(nb(n, 256)), dim3(256), 0, s, p, n, v);
 }
 
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {

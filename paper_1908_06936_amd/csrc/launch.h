@@ -32,7 +32,6 @@ void launch_finalize_loglik(const double* yv, int64_t n, const double* ldpart, i
                             hipStream_t s);
 void launch_finalize_grad(const double* part, int64_t nparts, double* out, hipStream_t s);
 void launch_fill_info(unsigned long long* info, hipStream_t s);
-void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 void launch_copy_diag_lower(double* dst, const double* diag, int64_t ts, int64_t NT, hipStream_t s);
 void launch_put_dinv(double* dst, const double* dinv, int64_t ts, int64_t NT, int c, hipStream_t s);
