@@ -352,6 +352,42 @@ def matern_cov_gc(lon, lat, theta) -> np.ndarray:
     return S
 
 
+def _dcov_gc(lon, lat, theta) -> np.ndarray:
+    """The three theta-derivative matrices of eq. (3) with great-circle distances."""
+    lon, lat = _f64(lon), _f64(lat)
+    n = lon.size
+    D = great_circle(lon[:, None], lat[:, None], lon[None, :], lat[None, :])
+    dS = np.zeros((3, n, n))
+    for i in range(n):
+        for j in range(i + 1):
+            g = matern_grad(D[i, j], theta)
+            dS[:, i, j] = g
+            dS[:, j, i] = g
+    return dS
+
+
+def fisher_gc(lon, lat, theta) -> np.ndarray:
+    """Fisher information (as `fisher`) with great-circle distances."""
+    S = matern_cov_gc(lon, lat, theta)
+    dS = _dcov_gc(lon, lat, theta)
+    A = [np.linalg.solve(S, dS[k]) for k in range(3)]
+    return np.array([[0.5 * np.sum(A[j] * A[k].T) for k in range(3)] for j in range(3)])
+
+
+def predict_gc(lon, lat, z, theta, lon_new, lat_new):
+    """Kriging (as `predict`) with great-circle distances; library Cholesky and
+    triangular solves as steps."""
+    import scipy.linalg
+
+    lon, lat, z = _f64(lon), _f64(lat), _f64(z)
+    n = lon.size
+    S = matern_cov_gc(np.concatenate([lon, _f64(lon_new)]), np.concatenate([lat, _f64(lat_new)]), theta)
+    L = np.linalg.cholesky(S[:n, :n])
+    v = scipy.linalg.solve_triangular(L, z, lower=True)
+    V = scipy.linalg.solve_triangular(L, S[:n, n:], lower=True)
+    return V.T @ v, _f64(theta)[0] - np.sum(V * V, axis=0)
+
+
 def loglik_grad_gc(lon, lat, z, theta):
     """(l, grad l) with great-circle distances; dense factorisation and inverse
     by library routines."""

@@ -668,3 +668,21 @@ def test_nugget_predict_single_observation(orc):
     mean, mse = orc.predict([0.3], [0.4], [z], [s2, 0.1, 0.8], [0.3], [0.4], nugget=t2)
     assert mean[0] == pytest.approx(s2 * z / (s2 + t2), rel=1e-14)
     assert mse[0] == pytest.approx(s2 * t2 / (s2 + t2), rel=1e-14)
+
+
+def test_great_circle_fisher_and_kriging(orc):
+    # Fisher: the variance entry n / (2 sigma^4) and invariance under a rotation
+    # in longitude; kriging: interpolation of the data and the prior at the
+    # antipode of a small cluster
+    u, v = inputgen.uniform(50, seed=61)
+    lon, lat = 40.0 * u - 20.0, 30.0 * v + 10.0
+    th = [1.3, 800.0, 0.8]
+    I = orc.fisher_gc(lon, lat, th)
+    assert I[0, 0] == pytest.approx(50 / (2 * th[0] ** 2), rel=1e-10)
+    np.testing.assert_allclose(orc.fisher_gc(lon + 123.0, lat, th), I, rtol=1e-9)
+    z = np.linalg.cholesky(orc.matern_cov_gc(lon, lat, th)) @ inputgen.normals(50, seed=61)
+    mean, mse = orc.predict_gc(lon, lat, z, th, lon[:5], lat[:5])
+    np.testing.assert_allclose(mean, z[:5], rtol=1e-9, atol=1e-9)
+    assert np.abs(mse).max() <= 1e-9
+    mean, mse = orc.predict_gc(lon, lat, z, th, [180.0], [-25.0])
+    assert abs(mean[0]) < 1e-8 and mse[0] == pytest.approx(th[0], rel=1e-12)  # correlations there ~ e^-22
