@@ -51,3 +51,27 @@ def test_great_circle_loglik_grad_vs_oracle(orc, exa, ts):
     assert ctx.timings()["frac_bf16"] == 0.0 and lm == pytest.approx(lref, rel=1e-6)
     ctx.set_distance("euclidean")
     assert ctx.loglik(dev(lon), dev(lat), dev(z), [0.8, 10.0, 0.6]) != pytest.approx(lref, rel=1e-3)
+
+
+def test_great_circle_fisher_vs_oracle(orc, exa):
+    lon, lat = lonlat(300, 84)
+    th = [1.1, 1200.0, 0.9]
+    ref = orc.fisher_gc(lon, lat, th)
+    ctx = exa.Context(ts=128)
+    ctx.set_distance("great_circle")
+    I = ctx.fisher(dev(lon), dev(lat), th)
+    d = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+    assert np.max(np.abs(I - ref) / d) <= 1e-9
+
+
+def test_great_circle_predict_vs_oracle(orc, exa):
+    lon, lat = lonlat(350, 85)
+    th = [0.9, 1000.0, 1.1]
+    z = np.linalg.cholesky(orc.matern_cov_gc(lon, lat, th)) @ inputgen.normals(350, seed=85)
+    lon_n, lat_n = lonlat(140, 86)
+    ref_mean, ref_mse = orc.predict_gc(lon, lat, z, th, lon_n, lat_n)
+    ctx = exa.Context(ts=128)
+    ctx.set_distance("great_circle")
+    mean, mse = ctx.predict(dev(lon), dev(lat), dev(z), th, dev(lon_n), dev(lat_n))
+    assert np.abs(mean.cpu().numpy() - ref_mean).max() <= 1e-9 * np.abs(z).max()
+    assert np.abs(mse.cpu().numpy() - ref_mse).max() <= 1e-9 * th[0]
