@@ -93,3 +93,26 @@ def test_nugget_rejects_invalid(exa):
     for bad in (-0.1, float("nan"), float("inf")):
         with pytest.raises(exa.ExaGeoError):
             ctx.set_nugget(bad)
+
+
+def test_nugget_with_mixed_precision_and_great_circle(orc, exa):
+    # the nugget sits on the FP64 diagonal tiles of the mixed factorisation,
+    # and composes with the great-circle distance
+    n, th, t2 = 700, [1.0, 0.05, 0.7], 0.2
+    x, y = inputgen.uniform(n, seed=120)
+    z = np.linalg.cholesky(orc.matern_cov_nugget(x, y, th, t2)) @ inputgen.normals(n, seed=120)
+    ref = orc.loglik_grad_nugget(x, y, z, th, t2)[0]
+    ctx = exa.Context(ts=128)
+    ctx.set_nugget(t2)
+    ctx.set_mixed_policy(0.0)
+    got = ctx.loglik(dev(x), dev(y), dev(z), th, "mixed")
+    assert got == pytest.approx(ref, rel=1e-6)
+    u, v = inputgen.uniform(400, seed=121)
+    lon, lat = 360.0 * u - 180.0, 150.0 * v - 75.0
+    thg = [0.8, 900.0, 0.6]
+    S = orc.matern_cov_gc(lon, lat, thg)
+    S[np.diag_indices_from(S)] += t2
+    L = np.linalg.cholesky(S)
+    zg = L @ inputgen.normals(400, seed=121)
+    ctx.set_distance("great_circle")
+    assert ctx.loglik(dev(lon), dev(lat), dev(zg), thg) == pytest.approx(orc.loglik_from_factor(L, zg), rel=1e-10)
