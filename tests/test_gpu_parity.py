@@ -106,11 +106,14 @@ def test_loglik_jittered_grid_vs_oracle(orc, ctx256, beta, nu):
     assert got == pytest.approx(ref, rel=1e-10)
 
 
-def test_loglik_config2_full_size(orc, exa):
-    # n = 10,000 (100 x 100 jittered grid), tile 512 (NT = 20, last tile 272):
-    # against the oracle's own covariance factored by LAPACK
+@pytest.mark.parametrize("nu", [0.5, 1.0])
+@pytest.mark.parametrize("beta", [0.03, 0.1, 0.3])
+def test_loglik_config2_full_size(orc, exa, beta, nu):
+    # n = 10,000 (100 x 100 jittered grid), tile 512 (NT = 20, last tile 272),
+    # every (beta, nu) of that study: against the oracle's own covariance
+    # factored by LAPACK
     x, y = inputgen.jittered_grid(100, seed=0)
-    th = [1.0, 0.1, 1.0]
+    th = [1.0, beta, nu]
     L = orc.dense_factor_lapack(x, y, th)
     z = L @ inputgen.normals(x.size, seed=0)
     ref = orc.loglik_from_factor(L, z)
