@@ -321,3 +321,41 @@ def test_mle_progress_lines(capfd, ctx768):
     err = capfd.readouterr().err
     lines = [s for s in err.splitlines() if s.startswith("[exageo_mle] eval")]
     assert len(lines) == stats["n_grad_evals"] + stats["n_evals"] and "fp64 +grad" in lines[0]
+
+
+def test_grad_central_differences_full_size(ctx768):
+    # the n = 40,000 (l, grad l) workload: 40,000 uniform points, theta = (1,
+    # 0.1, 1.0), tile 768, z simulated from the same field; central differences
+    # of the GPU l with h = 1e-6 theta_k.  l carries rounding noise of a few
+    # 1e-13 |l| (FP64 sums over 40,000 pivots and the quadratic form), which
+    # the difference quotient divides by h: the bound is 1e-12 |l| / h plus
+    # 1e-6 of |g_k| (d l / d sigma^2 = 40 is far below |l| / n here, so its
+    # check is noise-limited; the analytic score is pinned to 1e-8 against the
+    # oracle and by the Markov closed form elsewhere)
+    n = 40000
+    x, y = inputgen.uniform(n, seed=0)
+    th = np.array([1.0, 0.1, 1.0])
+    X, Y = dev(x), dev(y)
+    Z = ctx768.simulate(X, Y, list(th), dev(inputgen.normals(n, seed=0)))
+    ll, g = ctx768.loglik_grad(X, Y, Z, list(th))
+    for k in range(3):
+        h = 1e-6 * th[k]
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (ctx768.loglik(X, Y, Z, list(tp)) - ctx768.loglik(X, Y, Z, list(tm))) / (2 * h)
+        print(f"k={k}: analytic {g[k]:.12g} central difference {fd:.12g} rel {abs(g[k] - fd) / abs(g[k]):.2e}")
+        assert abs(g[k] - fd) <= 1e-6 * abs(g[k]) + 1e-12 * abs(ll) / h
+
+        # with steps 1e-4 and 2e-4 theta_k and Richardson's extrapolation the
+        # noise shrinks 100-fold and the truncation error stays O(h^4)
+        def cd(hk):
+            tp, tm = th.copy(), th.copy()
+            tp[k] += hk
+            tm[k] -= hk
+            return (ctx768.loglik(X, Y, Z, list(tp)) - ctx768.loglik(X, Y, Z, list(tm))) / (2 * hk)
+
+        H = 1e-4 * th[k]
+        rich = (4 * cd(H) - cd(2 * H)) / 3
+        print(f"k={k}: Richardson {rich:.12g} rel {abs(g[k] - rich) / abs(g[k]):.2e}")
+        assert abs(g[k] - rich) <= 1e-6 * abs(g[k]) + 2e-12 * abs(ll) / H
