@@ -71,3 +71,25 @@ def test_entry_points_reject_bad_arguments_before_any_launch(lib):
     assert lib.exageo_set_mixed_policy(None, 3.0) == EINVAL
     assert lib.exageo_set_mixed_fp64_band(None, 1.0) == EINVAL
     assert lib.exageo_last_error(None) == b"null context"
+
+
+def test_no_silent_cpu_path_without_a_gpu():
+    # the product path needs the GPU: without one it raises instead of falling back
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    import paper_1908_06936_amd as exa
+
+    with pytest.raises(RuntimeError):
+        exa.Context(ts=768)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
