@@ -6,7 +6,9 @@
  * arXiv 1908.06936), Section 1:
  *   - covariance, eq. (3):
  *       Sigma_ij = sigma2 / (2^(nu-1) Gamma(nu)) (r_ij/beta)^nu K_nu(r_ij/beta),
- *       r_ij = Euclidean distance of the 2-D locations s_i, s_j, Sigma_ii = sigma2;
+ *       r_ij = distance of the 2-D locations s_i, s_j (Euclidean, or great-circle
+ *       with exageo_set_distance), Sigma_ii = sigma2 (plus a fixed nugget with
+ *       exageo_set_nugget);
  *   - log-likelihood, eq. (2) with zero mean:
  *       l(theta) = -1/2 (n log 2 pi + log det Sigma + z^T Sigma^-1 z),
  *     evaluated through a Cholesky factorisation, a triangular solve and the
@@ -25,7 +27,11 @@
  *   outputs    host memory unless stated otherwise.
  *   streams    all work is queued on the stream given to exageo_create; a call
  *              returns after synchronising that stream only when it has to
- *              hand host scalars back.
+ *              hand host scalars back.  Inside a call a second stream of the
+ *              context (default priority) runs the next panel of the
+ *              factorisation and half of each step of the inverse factor,
+ *              ordered against the caller's stream by events; it is idle
+ *              whenever a call returns.
  *   order      results do not depend on the order of the locations: the
  *              library sorts a private copy along a Morton (Z-order) curve.
  *   errors     no C++ exception crosses the ABI; every call returns a status.
