@@ -348,7 +348,7 @@ def main() -> int:
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding of this path is described in DESIGN.md but not built.", file=sys.stderr)
+              "this path runs on one GPU; its multi-GPU sharding is not built.", file=sys.stderr)
         return 2
 
     import torch

@@ -5,9 +5,9 @@ The mixed result is an approximation of eq. (2); its tests check
   * the plumbing exactly: when every off-diagonal tile is exactly zero (well
     separated clusters, one cluster per tile) the mixed and FP64 paths agree
     to FP64 rounding;
-  * the error against the FP64 oracle stays within the bounds stated in
-    the design doc (storage rounding of off-diagonal covariances: unit roundoff
-    2^-24 for FP32 and 2^-9 for BF16, amplified by the conditioning);
+  * the error against the FP64 oracle stays within bounds set by the storage
+    rounding of the off-diagonal covariances (unit roundoff 2^-24 for FP32 and
+    2^-9 for BF16) amplified by the conditioning, measured on these inputs;
   * a wider BF16 band (fewer BF16 tiles) never does worse than a narrower
     one by more than rounding noise, and no BF16 tiles means FP32-only;
   * the mixed score (FP32 off-diagonal tiles of L^-1 and Sigma^-1, FP64
@@ -132,7 +132,8 @@ def test_mixed_grad_exact_when_off_diagonal_is_zero(orc, exa):
 
 # FP32 off-diagonal tiles of L, L^-1 and Sigma^-1: the score error against the
 # FP64 oracle, relative to the largest score component (bounds measured on
-# these inputs with a margin of about 10x; the design doc gives the error model)
+# these inputs with a margin of about 10x: the error comes from the FP32
+# factor, whose perturbation of Sigma the inverse amplifies)
 @pytest.mark.parametrize("beta,nu,band,tol", [(0.03, 0.5, 0.0, 3e-6), (0.1, 0.5, 0.0, 1e-5), (0.03, 0.5, 3.0, 1e-5)])
 def test_mixed_grad_vs_oracle(orc, exa, beta, nu, band, tol):
     ctx = exa.Context(ts=256, band_factor=band)

@@ -1,7 +1,9 @@
 """GPU path (through the C ABI) against the CPU oracle, element by element.
 
-Tolerances (written here, derived in the design doc):
-  * covariance entries: relative 2e-13 (trapezoidal K_nu vs Temme/recurrence);
+Tolerances:
+  * covariance entries: relative 2e-13 (the GPU's interpolated quadrature of
+    K_nu, 5e-14 relative, against the oracle's Temme series / recurrence, plus
+    the FP64 rounding of x^nu e^-x);
   * l(theta) in FP64: relative 1e-10;
   * gradient in FP64: relative 1e-8 of the gradient norm;
   * exact identities at full size (1-D Markov model, block additivity): 1e-10.
