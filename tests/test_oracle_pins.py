@@ -686,3 +686,22 @@ def test_great_circle_fisher_and_kriging(orc):
     assert np.abs(mse).max() <= 1e-9
     mean, mse = orc.predict_gc(lon, lat, z, th, [180.0], [-25.0])
     assert abs(mean[0]) < 1e-8 and mse[0] == pytest.approx(th[0], rel=1e-12)  # correlations there ~ e^-22
+
+
+@pytest.mark.slow
+def test_theta_recovery_with_fisher_standard_errors(orc):
+    # 16 simulated fields on a 15 x 15 jittered grid, theta = (1, 0.1, 0.5):
+    # the oracle's maximisers, standardised by the Fisher-information standard
+    # errors at the truth, have medians near 0 and spreads near 1 (a wrong
+    # score sign or a Fisher information off by a factor of 3 fails this)
+    x, y = inputgen.jittered_grid(15, seed=0)
+    th = np.array([1.0, 0.1, 0.5])
+    se = np.sqrt(np.diag(np.linalg.inv(orc.fisher(x, y, th))))
+    zs = []
+    for r in range(1, 17):
+        z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=r))
+        thh, _, _ = orc.mle(x, y, z, [0.01, 0.01, 0.05], [5.0, 2.0, 3.0], theta0=[0.8, 0.15, 0.6])
+        zs.append((thh - th) / se)
+    zs = np.array(zs)
+    assert np.all(np.abs(np.median(zs, axis=0)) < 1.5)
+    assert np.all((zs.std(axis=0) > 0.6) & (zs.std(axis=0) < 1.8))
