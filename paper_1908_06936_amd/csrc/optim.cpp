@@ -284,6 +284,9 @@ MleResult maximize_lbfgsb(const Objective& obj, const double lb[3], const double
       }
     }
     if (!accepted) {
+      // the search stopped for lack of evaluations or at a hard failure:
+      // not converged
+      if (!budget_left() || hard) break;
       if (mcount > 0) {
         mcount = 0;  // retry once from steepest descent
         continue;

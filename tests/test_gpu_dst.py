@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 import inputgen
+from scorecheck import assert_score_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -30,7 +31,7 @@ def test_dst_loglik_and_grad_vs_oracle(orc, exa, n, ts, band, th):
     l, g = ctx.loglik_grad(dev(x), dev(y), dev(z), th)
     print(f"n={n} band={band}: l rel {abs(l - lref) / abs(lref):.2e}, g rel {np.abs(np.asarray(g) - gref).max() / np.abs(gref).max():.2e}")
     assert l == pytest.approx(lref, rel=1e-10)
-    np.testing.assert_allclose(g, gref, rtol=1e-8, atol=1e-8 * np.abs(gref).max())
+    assert_score_close(g, gref, x.size, th)
     assert ctx.loglik(dev(x), dev(y), dev(z), th) == l
 
 

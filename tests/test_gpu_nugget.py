@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import inputgen
+from scorecheck import assert_score_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -43,7 +44,7 @@ def test_nugget_loglik_and_score_vs_oracle(orc, exa, n, ts, th, t2):
     ctx.set_nugget(t2)
     ll, g = ctx.loglik_grad(dev(x), dev(y), dev(z), th)
     assert ll == pytest.approx(ll_ref, rel=1e-10)
-    assert np.linalg.norm(np.array(g) - g_ref) <= 1e-8 * np.linalg.norm(g_ref)
+    assert_score_close(g, g_ref, n, th)
     assert ctx.loglik(dev(x), dev(y), dev(z), th) == pytest.approx(ll_ref, rel=1e-10)
 
 
