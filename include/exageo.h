@@ -185,6 +185,24 @@ exageo_status exageo_loglik_grad(exageo_ctx *ctx, int64_t n, const double *x, co
                                  const double *z, const double theta[3], int precision, double *loglik,
                                  double grad[3], int64_t *info);
 
+/* Allocation-free variant of exageo_loglik_grad, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same operation, arguments, statuses and
+ * FP64 arithmetic as exageo_loglik_grad with precision EXAGEO_FP64 (the
+ * context's distance, nugget and DST settings apply); grad may be NULL for
+ * l(theta) alone.  Its workspace is a fixed 128 MiB device array that the
+ * library holds on every GPU it runs on until the process ends (the context's
+ * own workspace is neither used nor allocated): ENOMEM, before any launch,
+ * when exageo_workspace_bytes(n, ts, EXAGEO_FP64, grad != NULL) exceeds
+ * 128 MiB (n up to about 4,000 at ts <= 512).  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).  Every call on one
+ * GPU shares that array, whatever the context: calls that overlap on one GPU
+ * (several host threads, or streams not ordered against each other) race and
+ * give wrong results. */
+exageo_status exageo_loglik_grad_noalloc(exageo_ctx *ctx, int64_t n, const double *x, const double *y,
+                                         const double *z, const double theta[3], double *loglik, double grad[3],
+                                         int64_t *info);
+
 /* Kriging (paper Sections 4 and 5, exact_predict): the conditional
  * distribution of the field at m new locations given the n observations, in
  * FP64,

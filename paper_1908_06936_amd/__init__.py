@@ -248,6 +248,27 @@ class Context:
         self._check(st, "loglik_grad", info.value)
         return ll.value, [g[0], g[1], g[2]]
 
+    def loglik_grad_noalloc(self, x, y, z, theta, with_grad: bool = True):
+        """(l, grad) like loglik_grad in FP64, on the library's fixed device
+        scratch: no device memory is allocated by this call (grad is None
+        when with_grad is False).  Returns (status, l, grad, info) without
+        raising, ENOMEM when n is above the scratch's limit."""
+        x = _dev_f64(x, "x")
+        n = x.numel()
+        y, z = _dev_f64(y, "y", n), _dev_f64(z, "z", n)
+        self._sync_stream()
+        ll = ctypes.c_double(0.0)
+        g = (ctypes.c_double * 3)()
+        info = ctypes.c_int64(0)
+        st = self._lib.exageo_loglik_grad_noalloc(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                                  ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                                  _lib.darr(theta), ctypes.byref(ll), g if with_grad else None,
+                                                  ctypes.byref(info))
+        return st, ll.value, ([g[0], g[1], g[2]] if with_grad else None), info.value
+
+    def last_error(self) -> str:
+        return self._lib.exageo_last_error(self._h).decode(errors="replace")
+
     def predict(self, x, y, z, theta, xnew, ynew, with_mse: bool = True):
         """Kriging at (xnew, ynew): (mean, mse) float64 tensors (mse None
         when with_mse is False)."""

@@ -32,7 +32,7 @@ EXPORTS = [
     "exageo_set_mixed_policy", "exageo_set_mixed_fp64_band", "exageo_set_dst_band", "exageo_set_distance", "exageo_set_nugget", "exageo_set_verbose", "exageo_last_error",
     "exageo_matern_cov",
     "exageo_simulate", "exageo_loglik",
-    "exageo_loglik_grad", "exageo_mle", "exageo_predict", "exageo_fisher", "exageo_get_timings", "exageo_set_profiling",
+    "exageo_loglik_grad", "exageo_loglik_grad_noalloc", "exageo_mle", "exageo_predict", "exageo_fisher", "exageo_get_timings", "exageo_set_profiling",
 ]
 
 _lib = None
@@ -81,6 +81,8 @@ def load():
     lib.exageo_loglik.argtypes = [p, i64, p, p, p, pd, i32, pd, pi64]
     lib.exageo_loglik_grad.restype = st
     lib.exageo_loglik_grad.argtypes = [p, i64, p, p, p, pd, i32, pd, pd, pi64]
+    lib.exageo_loglik_grad_noalloc.restype = st
+    lib.exageo_loglik_grad_noalloc.argtypes = [p, i64, p, p, p, pd, pd, pd, pi64]
     lib.exageo_predict.restype = st
     lib.exageo_predict.argtypes = [p, i64, p, p, p, pd, i64, p, p, p, p, pi64]
     lib.exageo_fisher.restype = st

@@ -15,6 +15,7 @@
 
 #include "launch.h"
 #include "mle.h"
+#include "noalloc.h"
 
 namespace {
 
@@ -116,6 +117,9 @@ struct exageo_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool ws_owned = false;
+  // device address of this device's fixed scratch array (allocation-free
+  // entry point), looked up when the context is created
+  void* scratch = nullptr;
   // pinned host staging for results
   double* hres = nullptr;
   // current plan and sorted-location cache key (only valid inside one call or an MLE run)
@@ -598,7 +602,8 @@ exageo_status exageo_create(exageo_ctx** out, int device, int64_t ts, void* hip_
   if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void**)&c->hres, 64 * sizeof(double)) != hipSuccess ||
       hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_col, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_panel, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_panel, hipEventDisableTiming) != hipSuccess ||
+      exg::scratch_address(device, &c->scratch) != hipSuccess) {
     exageo_destroy(c);
     return EXAGEO_EDEVICE;
   }
@@ -801,6 +806,36 @@ exageo_status exageo_loglik_grad(exageo_ctx* c, int64_t n, const double* x, cons
                                  const double theta[3], int precision, double* loglik, double grad[3],
                                  int64_t* info) {
   return loglik_common(c, n, x, y, z, theta, precision, loglik, grad, info, true);
+}
+
+exageo_status exageo_loglik_grad_noalloc(exageo_ctx* c, int64_t n, const double* x, const double* y,
+                                         const double* z, const double theta[3], double* loglik, double grad[3],
+                                         int64_t* info) {
+  if (!c) return EXAGEO_EINVAL;
+  c->err.clear();
+  if (info) *info = 0;
+  if (n < 1 || !x || !y || !z || !theta_ok(theta) || !loglik)
+    return fail(c, EXAGEO_EINVAL, "loglik_grad_noalloc: invalid argument");
+  if (!c->scratch) return fail(c, EXAGEO_EDEVICE, "loglik_grad_noalloc: no scratch address for this device");
+  const bool want_grad = grad != nullptr;
+  const size_t need = make_plan(n, c->ts, want_grad, EXAGEO_FP64).bytes;
+  if (need > exg::kScratchBytes)
+    return fail(c, EXAGEO_ENOMEM,
+                "loglik_grad_noalloc: n = %lld with tile %lld needs %zu bytes, above the %zu-byte fixed scratch",
+                (long long)n, (long long)c->ts, need, exg::kScratchBytes);
+  // run the ordinary pipeline on the fixed scratch: it fits, so nothing is
+  // allocated; the context's own workspace is restored afterwards
+  char* ws = c->ws;
+  const size_t ws_bytes = c->ws_bytes;
+  const bool ws_owned = c->ws_owned;
+  c->ws = (char*)c->scratch;
+  c->ws_bytes = exg::kScratchBytes;
+  c->ws_owned = false;
+  const exageo_status st = loglik_common(c, n, x, y, z, theta, EXAGEO_FP64, loglik, grad, info, want_grad);
+  c->ws = ws;
+  c->ws_bytes = ws_bytes;
+  c->ws_owned = ws_owned;
+  return st;
 }
 
 exageo_status exageo_simulate(exageo_ctx* c, int64_t n, const double* x, const double* y, const double theta[3],
