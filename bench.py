@@ -70,6 +70,18 @@ def traffic_bytes():
     return TRAFFIC_BYTES_PER_LAUNCH if traffic_fingerprint() == TRAFFIC_FINGERPRINT else None
 
 
+def set_map(ctx, mp):
+    """Mixed-precision map of a context: 'default' (the library's correlation
+    map with one refinement step), 'fp32' (distance map without BF16 or FP64
+    tiles) or 'bf16_3beta' (BF16 beyond 3 beta), the last two unrefined."""
+    if mp in (None, "default"):
+        ctx.set_mixed_correlation()
+        ctx.set_mixed_refinement(1)
+    else:
+        ctx.set_mixed_policy(0.0 if mp == "fp32" else 3.0, 0.0)
+        ctx.set_mixed_refinement(0)
+
+
 def cpu_baseline(n_full: int, theta, sizes=(400, 700, 1000)) -> dict:
     """The oracle (CPU, FP64) timed on one host core, extrapolated to n_full.
 
@@ -168,19 +180,20 @@ def mle_study(args) -> int:
     del ctx
 
     # n = 40,000: estimators compared, for a rough (nu = 0.5) and a smoother
-    # (nu = 0.8) field; evaluation caps keep each run within a few minutes
+    # (nu = 0.8) field; evaluation caps keep each run within a few minutes.
+    # Mixed precision uses the library's default map (tiles by correlation
+    # bound, one FP64 refinement step of Sigma^-1 z).
     lb, ub, th0 = [0.01, 0.01, 0.1], [5.0, 2.0, 3.0], [0.5, 0.3, 0.5]
     out["n40000_grid"] = {}
+    all_est = {"fp64_dfo": ("dfo", "fp64", 400), "fp64_lbfgsb": ("lbfgsb", "fp64", 80),
+               "mixed_lbfgsb": ("lbfgsb", "mixed", 80), "mixed_lbfgsb_fp64_finish": ("lbfgsb_fp64_finish", "mixed", 80),
+               "mixed_dfo": ("dfo", "mixed", 400)}
+    chosen = args.mle_estimators or ["fp64_dfo", "fp64_lbfgsb", "mixed_lbfgsb", "mixed_lbfgsb_fp64_finish"]
     for th_true in [[1.0, 0.1, nu] for nu in (args.mle_nus if not args.mle_skip_40k else [])]:
         ctx, X, Y, Z = field(200, th_true, 1, 768)
         runs = {}
-        estimators = [("fp64_dfo", "dfo", "fp64", 400), ("fp64_lbfgsb", "lbfgsb", "fp64", 80),
-                      ("mixed_lbfgsb_fp64_finish", "lbfgsb_fp64_finish", "mixed", 80)]
-        if args.mle_all:
-            estimators += [("mixed_lbfgsb", "lbfgsb", "mixed", 80), ("mixed_dfo", "dfo", "mixed", 400)]
-        for label, meth, prec, cap in estimators:
-            # mixed: FP32 off-diagonal tiles with the FP64 band at 0.5 beta, no BF16
-            ctx.set_mixed_policy(0.0, 0.5)
+        for label in chosen:
+            meth, prec, cap = all_est[label]
             t0 = time.perf_counter()
             try:
                 th_hat, l_hat, st = ctx.mle(X, Y, Z, lb, ub, theta0=th0, tol=1e-4, max_iters=cap, method=meth,
@@ -192,14 +205,15 @@ def mle_study(args) -> int:
             l64 = ctx.loglik_status(X, Y, Z, th_hat, "fp64")[1]
             runs[label] = {"theta_hat": th_hat, "loglik_reported": l_hat, "loglik_fp64_at_theta_hat": l64,
                            "wall_s": wall, "max_evals": cap, "stats": st,
-                           "mixed_policy": "FP32 off-diagonal, FP64 band 0.5 beta" if prec == "mixed" else None}
+                           "mixed_policy": "default correlation map, 1 refinement step" if prec == "mixed" else None}
             print(f"[mle] n=40000 nu={th_true[2]} {label}: {wall:.1f} s, theta {th_hat}, {st}", file=sys.stderr,
                   flush=True)
-        ref = runs.get("fp64_dfo", {}).get("loglik_fp64_at_theta_hat")
+        refl = "fp64_dfo" if "fp64_dfo" in runs else "fp64_lbfgsb"
+        ref = runs.get(refl, {}).get("loglik_fp64_at_theta_hat")
         for label, d in runs.items():
             if ref is not None and "loglik_fp64_at_theta_hat" in d:
-                d["rel_dl_vs_fp64_dfo"] = abs(d["loglik_fp64_at_theta_hat"] - ref) / abs(ref)
-                d["speedup_vs_fp64_dfo"] = runs["fp64_dfo"]["wall_s"] / d["wall_s"]
+                d[f"rel_dl_vs_{refl}"] = abs(d["loglik_fp64_at_theta_hat"] - ref) / abs(ref)
+                d[f"speedup_vs_{refl}"] = runs[refl]["wall_s"] / d["wall_s"]
         out["n40000_grid"][f"nu={th_true[2]}"] = {"theta_true": th_true, "theta0": th0, "lb": lb, "ub": ub,
                                                   "runs": runs}
         ctx.close()
@@ -213,8 +227,7 @@ def mle_study(args) -> int:
         print(json.dumps(out))
         return 0
     ctx, X, Y, Z = field(m, th_true, 2, 768)
-    ctx.set_mixed_policy(0.0, 0.5)
-    big = {"n": m * m, "mixed_policy": "FP32 off-diagonal, FP64 band 0.5 beta"}
+    big = {"n": m * m, "mixed_policy": "default correlation map, 1 refinement step"}
     for label, prec, grad in (("fp64_loglik", "fp64", False), ("fp64_loglik_grad", "fp64", True),
                               ("mixed_loglik_grad", "mixed", True)):
         torch.cuda.synchronize()
@@ -263,8 +276,13 @@ def mle_large(args) -> int:
     torch.cuda.synchronize()
     lb, ub, th0 = [0.01, 0.001, 0.1], [5.0, 2.0, 3.0], [0.5, 0.3, 0.5]
     meth, prec = {"fp64_lbfgsb": ("lbfgsb", "fp64"), "fp64_dfo": ("dfo", "fp64"), "mixed_dfo": ("dfo", "mixed"),
+                  "mixed_lbfgsb": ("lbfgsb", "mixed"),
                   "mixed_lbfgsb_fp64_finish": ("lbfgsb_fp64_finish", "mixed")}[args.mle_estimator]
-    ctx.set_mixed_policy(3.0 if args.mle_policy == "bf16_3beta" else 0.0)
+    if args.mle_policy == "default":
+        ctx.set_mixed_correlation()  # the library's default map
+    else:
+        ctx.set_mixed_policy(3.0 if args.mle_policy == "bf16_3beta" else 0.0)
+        ctx.set_mixed_refinement(0)
     ctx.set_verbose(True)
     print(f"[mle-large] n={x.size} beta={beta} {args.mle_estimator} policy={args.mle_policy} cap={args.mle_cap}",
           file=sys.stderr, flush=True)
@@ -283,45 +301,141 @@ def mle_large(args) -> int:
     return 0
 
 
+PRECISION_POLICIES = {
+    # label: (kind, parameters, refinement steps)
+    "corr_0.3_1e-4": ("corr", (0.3, 1e-4), 1),
+    "corr_0.3_1e-4_norefine": ("corr", (0.3, 1e-4), 0),
+    "corr_0.3_1e-4_refine2": ("corr", (0.3, 1e-4), 2),
+    "corr_0.5_1e-3": ("corr", (0.5, 1e-3), 1),
+    "corr_0.1_1e-5": ("corr", (0.1, 1e-5), 1),
+    "corr_0.3_nobf16": ("corr", (0.3, 0.0), 1),
+    "dist_fp32_only": ("dist", (0.0, 0.0), 0),
+    "dist_bf16_3beta": ("dist", (3.0, 0.0), 0),
+    "dist_fp32_fp64band_0.5beta": ("dist", (0.0, 0.5), 0),
+}
+
+
+def _apply_policy(ctx, label):
+    kind, prm, refine = PRECISION_POLICIES[label]
+    if kind == "corr":
+        ctx.set_mixed_correlation(*prm)
+    else:
+        ctx.set_mixed_policy(*prm)
+    ctx.set_mixed_refinement(refine)
+
+
 def precision_study(args) -> int:
-    """l in FP64 and in mixed precision at n = 90,000 (300 x 300 jittered grid,
-    theta = (1, beta, 0.5), beta in {0.03, 0.1}, tile 768): relative
-    difference, wall clock and tile fractions for FP32 off-diagonal tiles,
-    FP32 with an FP64 band of 0.5 beta, and BF16 beyond 3 beta (one JSON line)."""
+    """l (and, where asked, (l, grad l)) in FP64 and under several mixed-
+    precision maps (one JSON line): the relative error of l against the FP64
+    path split into its log-det and quadratic-form parts, the score error per
+    component relative to max |g|, tile fractions, and times.
+
+    Fields (tile 768): the 300 x 300 jittered grid (n = 90,000, theta = (1,
+    beta, 0.5), beta in {0.03, 0.1}); the 200 x 200 jittered grid (n = 40,000,
+    beta in {0.03, 0.1}, nu in {0.5, 1.0}, with scores); the n = 40,000
+    uniform field of the headline workload (nu = 1); sorted points on a line
+    with mean gap 5e-4 (n = 40,000, beta = 0.1, nu = 0.5), whose exact l is
+    the O(n) Markov closed form.  --precision-policies picks the maps."""
+    import math
+
+    import numpy as np
     import torch
 
     import inputgen
     import paper_1908_06936_amd as exa
 
     dev = torch.device("cuda:0")
-    x, y = inputgen.jittered_grid(300, seed=0)
-    e = inputgen.normals(x.size, seed=0)
-    X, Y, E = (torch.as_tensor(a, device=dev) for a in (x, y, e))
     ctx = exa.Context(ts=768)
-    out = {"study": "precision", "n": int(x.size), "data": "synthetic", "grid": "300x300 jittered, seed 0"}
-    for beta in (0.03, 0.1):
-        th = [1.0, beta, 0.5]
-        Z = ctx.simulate(X, Y, th, E)
+    labels = args.precision_policies or list(PRECISION_POLICIES)
+    out = {"study": "precision", "data": "synthetic", "policies": {k: PRECISION_POLICIES[k] for k in labels}}
+
+    def run(name, X, Y, Z, th, with_grad, exact=None):
         res = {}
-        for label, prec, bf, f64 in (("fp64", "fp64", 3.0, 0.0), ("mixed_fp32", "mixed", 0.0, 0.0),
-                                     ("mixed_fp32_fp64band", "mixed", 0.0, 0.5), ("mixed_bf16_3beta", "mixed", 3.0, 0.0),
-                                     ("mixed_bf16_3beta_fp64band", "mixed", 3.0, 0.5)):
-            ctx.set_mixed_policy(bf, f64)
-            ctx.loglik_status(X, Y, Z, th, prec)  # warm-up
+        for label in ["fp64"] + labels:
+            prec = "fp64" if label == "fp64" else "mixed"
+            if label != "fp64":
+                _apply_policy(ctx, label)
+            st, v, info = ctx.loglik_status(X, Y, Z, th, prec)  # warm-up / status
+            if st != 0:
+                res[label] = {"status": exa.STATUS_NAMES.get(st, st), "info": info}
+                print(f"[precision] {name} {label}: status {res[label]['status']}", file=sys.stderr, flush=True)
+                continue
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st, v, info = ctx.loglik_status(X, Y, Z, th, prec)
+            v = ctx.loglik(X, Y, Z, th, prec)
             torch.cuda.synchronize()
+            t1 = time.perf_counter()
             tm = ctx.timings()
-            res[label] = {"status": exa.STATUS_NAMES.get(st, st), "loglik": v, "s": time.perf_counter() - t0,
-                          "frac_bf16": tm.get("frac_bf16"), "frac_fp64_band": tm.get("frac_fp64")}
-            print(f"[precision] beta={beta} {label}: {res[label]}", file=sys.stderr, flush=True)
-        l64 = res["fp64"]["loglik"]
-        for d in res.values():
-            if d["status"] == "OK":
-                d["rel_dl_vs_fp64"] = abs(d["loglik"] - l64) / abs(l64)
-                d["speedup_vs_fp64"] = res["fp64"]["s"] / d["s"]
-        out[f"beta={beta}"] = res
+            d = {"status": "OK", "loglik": v, "loglik_s": t1 - t0, "logdet": tm["logdet"], "quad_form": tm["quad_form"],
+                 "frac_bf16": tm.get("frac_bf16"), "frac_fp64": tm.get("frac_fp64"), "frac_fp32": tm.get("frac_fp32")}
+            if with_grad:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, g = ctx.loglik_grad(X, Y, Z, th, prec)
+                torch.cuda.synchronize()
+                d["grad"] = g
+                d["loglik_grad_s"] = time.perf_counter() - t0
+            res[label] = d
+            print(f"[precision] {name} {label}: l {v:.12g} ({d['loglik_s']:.3f} s) bf16 {d['frac_bf16']} "
+                  f"fp64 {d['frac_fp64']}", file=sys.stderr, flush=True)
+        ref = res["fp64"]
+        for label, d in res.items():
+            if d.get("status") != "OK":
+                continue
+            if exact is not None:
+                d["rel_err_vs_exact"] = abs(d["loglik"] - exact) / abs(exact)
+            if label == "fp64" or ref.get("status") != "OK":
+                continue
+            L = abs(ref["loglik"])
+            d["rel_err_vs_fp64"] = abs(d["loglik"] - ref["loglik"]) / L
+            d["rel_err_logdet_part"] = 0.5 * abs(d["logdet"] - ref["logdet"]) / L
+            d["rel_err_quad_part"] = 0.5 * abs(d["quad_form"] - ref["quad_form"]) / L
+            d["speedup_l"] = ref["loglik_s"] / d["loglik_s"]
+            if with_grad:
+                gmax = max(abs(q) for q in ref["grad"])
+                d["grad_err_over_max_abs_grad"] = [abs(a - b) / gmax for a, b in zip(d["grad"], ref["grad"])]
+                d["grad_rel_err_per_component"] = [abs(a - b) / abs(b) for a, b in zip(d["grad"], ref["grad"])]
+                d["speedup_l_grad"] = ref["loglik_grad_s"] / d["loglik_grad_s"]
+        out[name] = res
+
+    # config 4: 300 x 300 jittered grid
+    if not args.precision_skip_90k:
+        x, y = inputgen.jittered_grid(300, seed=0)
+        X, Y = torch.as_tensor(x, device=dev), torch.as_tensor(y, device=dev)
+        E = torch.as_tensor(inputgen.normals(x.size, seed=0), device=dev)
+        for beta in (0.03, 0.1):
+            th = [1.0, beta, 0.5]
+            Z = ctx.simulate(X, Y, th, E)
+            run(f"grid300_beta{beta}_nu0.5", X, Y, Z, th, False)
+        del X, Y, E, Z
+    # 200 x 200 jittered grid with scores
+    x, y = inputgen.jittered_grid(200, seed=0)
+    X, Y = torch.as_tensor(x, device=dev), torch.as_tensor(y, device=dev)
+    E = torch.as_tensor(inputgen.normals(x.size, seed=0), device=dev)
+    for beta, nu in ((0.03, 0.5), (0.1, 0.5), (0.1, 1.0)):
+        th = [1.0, beta, nu]
+        Z = ctx.simulate(X, Y, th, E)
+        run(f"grid200_beta{beta}_nu{nu}", X, Y, Z, th, True)
+    # the headline field: 40,000 uniform points, nu = 1
+    x, y = inputgen.uniform(40000, seed=0)
+    X, Y = torch.as_tensor(x, device=dev), torch.as_tensor(y, device=dev)
+    th = [1.0, 0.1, 1.0]
+    Z = ctx.simulate(X, Y, th, E)
+    run("uniform40000_beta0.1_nu1.0", X, Y, Z, th, True)
+    # Markov line: exact l in O(n)
+    n, s2, beta = 40000, 1.0, 0.1
+    t, y0 = inputgen.collinear(n, mean_gap=5e-4, seed=11)
+    e = inputgen.normals(n, seed=11)
+    rho = np.exp(-np.diff(t) / beta)
+    z = np.empty(n)
+    z[0] = math.sqrt(s2) * e[0]
+    for i in range(1, n):
+        z[i] = rho[i - 1] * z[i - 1] + math.sqrt(s2 * (1 - rho[i - 1] ** 2)) * e[i]
+    v = s2 * (1 - rho ** 2)
+    exact = -0.5 * (math.log(2 * math.pi) + math.log(s2) + z[0] ** 2 / s2)
+    exact += float(np.sum(-0.5 * (math.log(2 * math.pi) + np.log(v) + (z[1:] - rho * z[:-1]) ** 2 / v)))
+    X, Y, Z = (torch.as_tensor(a, device=dev) for a in (t, y0, z))
+    run("markov_line40000_gap5e-4", X, Y, Z, [s2, beta, 0.5], False, exact=exact)
     print(json.dumps(out))
     return 0
 
@@ -343,18 +457,23 @@ def main() -> int:
                          "gradient-based and mixed precision) and single evaluations at n = 160,000")
     ap.add_argument("--big-n-side", type=int, default=400,
                     help="grid side of the large single evaluations (0: skip them)")
-    ap.add_argument("--mle-all", action="store_true", help="also the plain mixed-precision estimators")
+    ap.add_argument("--mle-estimators", nargs="+", default=None,
+                    choices=["fp64_dfo", "fp64_lbfgsb", "mixed_lbfgsb", "mixed_lbfgsb_fp64_finish", "mixed_dfo"],
+                    help="estimators of --mle-study at n = 40,000 (default: all but mixed_dfo)")
     ap.add_argument("--mle-nus", type=float, nargs="+", default=[0.5, 0.8], help="true nu of the n = 40,000 fields")
     ap.add_argument("--mle-skip-40k", action="store_true", help="--mle-study without the n = 40,000 estimators")
     ap.add_argument("--mle-large", action="store_true",
                     help="instead of the throughput step: one estimator on the --big-n-side grid (see mle_large)")
     ap.add_argument("--mle-beta", type=float, default=0.03)
     ap.add_argument("--mle-estimator", default="fp64_lbfgsb",
-                    choices=["fp64_lbfgsb", "fp64_dfo", "mixed_dfo", "mixed_lbfgsb_fp64_finish"])
-    ap.add_argument("--mle-policy", default="bf16_3beta", choices=["fp32", "bf16_3beta"])
+                    choices=["fp64_lbfgsb", "fp64_dfo", "mixed_dfo", "mixed_lbfgsb", "mixed_lbfgsb_fp64_finish"])
+    ap.add_argument("--mle-policy", default="default", choices=["default", "fp32", "bf16_3beta"])
     ap.add_argument("--mle-cap", type=int, default=60, help="evaluation cap of --mle-large")
     ap.add_argument("--precision-study", action="store_true",
-                    help="instead of the throughput step: FP64 vs mixed-precision l on a 300 x 300 jittered grid")
+                    help="instead of the throughput step: FP64 vs mixed-precision l and scores under several "
+                         "precision maps (see precision_study)")
+    ap.add_argument("--precision-policies", nargs="+", choices=sorted(PRECISION_POLICIES), default=None)
+    ap.add_argument("--precision-skip-90k", action="store_true")
     args = ap.parse_args()
 
     if args.copy_calibration:
@@ -500,14 +619,16 @@ def main() -> int:
     if args.no_mixed:
         print(json.dumps(result))
         return 0
-    # l(theta) alone, FP64 and mixed precision (FP64 diagonal tiles, FP32
-    # off-diagonal tiles; BF16 beyond band * beta), same inputs (the smooth
-    # nu = 1 field on uniform points is too ill-conditioned for FP32 tiles:
-    # the mixed factorisation then reports ENOTPD)
+    # l(theta) alone, FP64 and mixed precision on the same inputs: the
+    # library's default map (tiles by correlation bound, one FP64 refinement
+    # step) and, for the record, the distance maps FP32-only and BF16 beyond
+    # 3 beta without refinement (this smooth nu = 1 field on uniform points
+    # does not factor with FP32 tiles next to the diagonal: ENOTPD)
     ctx.set_profiling(False)
     ll_only = {}
-    for label, prec, band in (("fp64", "fp64", 3.0), ("mixed_fp32", "mixed", 0.0), ("mixed_bf16_3beta", "mixed", 3.0)):
-        ctx.set_mixed_policy(band)
+    for label, prec, mp in (("fp64", "fp64", None), ("mixed_default_map", "mixed", "default"),
+                               ("mixed_fp32_only", "mixed", "fp32"), ("mixed_bf16_3beta", "mixed", "bf16_3beta")):
+        set_map(ctx, mp)
         st, v, info = ctx.loglik_status(X, Y, Z, theta, prec)  # warm-up / status
         if st != 0:
             ll_only[label] = {"status": exa.STATUS_NAMES.get(st, st), "info": info}
@@ -519,10 +640,23 @@ def main() -> int:
             v = ctx.loglik(X, Y, Z, theta, prec)
         torch.cuda.synchronize()
         rate = args.steps / (time.perf_counter() - t1)
+        tmo = ctx.timings()
         ll_only[label] = {"status": "OK", "evals_per_s": rate, "loglik": v,
-                          "frac_bf16_tiles": ctx.timings().get("frac_bf16")}
+                          "frac_bf16_tiles": tmo.get("frac_bf16"), "frac_fp64_tiles": tmo.get("frac_fp64")}
+        if label == "mixed_default_map":
+            # (l, grad l) in mixed precision on the headline field
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                lg, gg = ctx.loglik_grad(X, Y, Z, theta, prec)
+            torch.cuda.synchronize()
+            ll_only[label]["loglik_grad_evals_per_s"] = args.steps / (time.perf_counter() - t1)
+            ll_only[label]["grad"] = gg
+            g64 = result["grad"]
+            gmax = max(abs(q) for q in g64)
+            ll_only[label]["grad_err_vs_fp64_over_max_abs_grad"] = [abs(a - b) / gmax for a, b in zip(gg, g64)]
         print(f"[bench] loglik-only {label}: {rate:.3f} evals/s", file=sys.stderr, flush=True)
-    ctx.set_mixed_policy(3.0)
+    set_map(ctx, "default")
     l64 = ll_only["fp64"].get("loglik")
     for label, d in ll_only.items():
         if label != "fp64" and "loglik" in d and l64 is not None:
@@ -539,9 +673,9 @@ def main() -> int:
         Zg = ctx.simulate(Xg, Yg, th_g, E)
         key = f"beta={th_g[1]},nu={th_g[2]}"
         grid[key] = {}
-        for label, prec, band in (("fp64", "fp64", 3.0), ("mixed_fp32", "mixed", 0.0),
-                                  ("mixed_bf16_3beta", "mixed", 3.0)):
-            ctx.set_mixed_policy(band)
+        for label, prec, mp in (("fp64", "fp64", None), ("mixed_default_map", "mixed", "default"),
+                               ("mixed_fp32_only", "mixed", "fp32"), ("mixed_bf16_3beta", "mixed", "bf16_3beta")):
+            set_map(ctx, mp)
             st, v, info = ctx.loglik_status(Xg, Yg, Zg, th_g, prec)
             if st != 0:
                 grid[key][label] = {"status": exa.STATUS_NAMES.get(st, st), "info": info}
@@ -566,7 +700,7 @@ def main() -> int:
             upd = tm["update_flops"] / (tm["update_kernel_ms"] * 1e-3) / 1e12
             grid[key][label] = {"status": "OK", "loglik_evals_per_s": args.steps / (t2 - t1),
                                 "loglik_grad_evals_per_s": args.steps / (t3 - t2), "loglik": v, "grad": gg,
-                                "frac_bf16_tiles": tm.get("frac_bf16"),
+                                "frac_bf16_tiles": tm.get("frac_bf16"), "frac_fp64_tiles": tm.get("frac_fp64"),
                                 "update_flop_shares_fp32_bf16_fp64": [f / sum(fl) for f in fl],
                                 "update_tflops": upd, "update_weighted_peak_tflops": wpeak,
                                 "update_frac_of_weighted_peak": upd / wpeak}
@@ -578,7 +712,7 @@ def main() -> int:
                 d["grad_err_vs_fp64_over_max_abs_grad"] = [abs(a - b) / gmax for a, b in zip(d["grad"], ref["grad"])]
                 d["loglik_grad_speedup_vs_fp64"] = d["loglik_grad_evals_per_s"] / ref["loglik_grad_evals_per_s"]
         print(f"[bench] jittered grid {key} done", file=sys.stderr, flush=True)
-    ctx.set_mixed_policy(3.0)
+    set_map(ctx, "default")
     result["fp64_vs_mixed_jittered_grid_200x200"] = grid
     g03 = grid.get("beta=0.03,nu=0.5", {})
     result["mixed_summary"] = {

@@ -59,9 +59,11 @@ typedef int32_t exageo_status;
 
 /* precision of the factorisation */
 #define EXAGEO_FP64 0  /* every tile in double precision                      */
-#define EXAGEO_MIXED 1 /* diagonal tiles FP64, off-diagonal FP32, and BF16 for
-                          tiles whose location boxes are farther apart than
-                          band_factor * beta (Section 2.1, Fig. 1(d))         */
+#define EXAGEO_MIXED 1 /* diagonal tiles FP64; each off-diagonal tile FP64,
+                          FP32 or BF16 by the precision map (Section 2.1,
+                          Fig. 1(d)): by default from the largest correlation
+                          of the tile (exageo_set_mixed_correlation), or by
+                          distance bands (exageo_set_mixed_policy)           */
 
 /* optimiser of exageo_mle */
 #define EXAGEO_DFO 0    /* derivative-free bounded search on l(theta)         */
@@ -110,20 +112,45 @@ size_t exageo_workspace_bytes(int64_t n, int64_t ts, int precision, int want_gra
  * allocation (hipMalloc, grown on demand, freed by exageo_destroy). */
 exageo_status exageo_set_workspace(exageo_ctx *ctx, void *dev_ptr, size_t bytes);
 
-/* Band of the mixed-precision policy: an off-diagonal tile is stored and
- * updated in BF16 when the minimum distance between the bounding boxes of its
- * two location blocks is at least band_factor * beta, else in FP32.
- * 0 disables BF16 (FP32 off-diagonal only).  Default 3.0.  EINVAL if < 0. */
-exageo_status exageo_set_mixed_policy(exageo_ctx *ctx, double band_factor);
+/* Precision map of EXAGEO_MIXED by correlation (the default, with
+ * fp64_at_or_above = 0.3 and bf16_below = 1e-4).  The paper's mixed-precision
+ * structure keeps double-precision tiles near the diagonal and single or half
+ * precision farther out (Section 2.1, Fig. 1(d)) without a rule; here, with
+ * the locations in the library's Z-order cut into tiles, c_ij = the Matern
+ * correlation (eq. (3) divided by sigma2) at the smallest distance between the
+ * bounding boxes of location blocks i and j bounds every |Sigma_ab| / sigma2
+ * of tile (i, j), and the tile is
+ *   FP64 when c_ij >= fp64_at_or_above,
+ *   BF16 when c_ij < bf16_below and c_ik c_jk < bf16_below for every k < j
+ *        (the BF16 update multiplies BF16 roundings of L_ik and L_jk),
+ *   FP32 otherwise.
+ * FP64 tiles live in a pool of max(4 NT, half the off-diagonal tiles); when
+ * more qualify, the most correlated are FP64 and the rest FP32 (the FP64
+ * fraction is reported by exageo_get_timings).  With great-circle distances
+ * every off-diagonal tile is FP32.  EINVAL unless 0 <= bf16_below <=
+ * fp64_at_or_above (a value above 1 switches FP64 tiles off, 0 switches BF16
+ * off).  Applies to later calls; switches the context to this policy. */
+exageo_status exageo_set_mixed_correlation(exageo_ctx *ctx, double fp64_at_or_above, double bf16_below);
 
-/* FP64 band of the mixed-precision policy (the double-precision tiles near
- * the diagonal of the paper's mixed-precision structure, Section 2.1 and
- * Fig. 1(d)): an off-diagonal tile whose two location blocks have bounding
- * boxes closer than fp64_band_factor * beta is stored and updated in FP64,
- * closest first, up to 4 NT such tiles (the rest stay FP32).  The BF16 band
- * takes precedence.  0 (default) keeps every off-diagonal tile in FP32 or
- * BF16.  EINVAL if < 0. */
+/* Precision map of EXAGEO_MIXED by distance bands (switches the context to
+ * this policy): an off-diagonal tile is stored and updated in BF16 when the
+ * minimum distance between the bounding boxes of its two location blocks is
+ * at least band_factor * beta (0 disables BF16), in FP64 when it is below
+ * fp64_band_factor * beta (exageo_set_mixed_fp64_band, default 0; closest
+ * first within the pool above; the BF16 band takes precedence), else in
+ * FP32.  Default band_factor 3.0.  EINVAL if < 0. */
+exageo_status exageo_set_mixed_policy(exageo_ctx *ctx, double band_factor);
 exageo_status exageo_set_mixed_fp64_band(exageo_ctx *ctx, double fp64_band_factor);
+
+/* Refinement of a = Sigma^-1 z in EXAGEO_MIXED (default 1 step, at most 8):
+ * after the solves through the mixed factor, each step forms the residual
+ * r = z - Sigma a in FP64 with Sigma regenerated on the fly (n^2 covariance
+ * evaluations, no stored matrix) and adds (mixed factor)^-1 r to a.  l then
+ * uses the quadratic form z^T a, and the score the refined a in its
+ * a^T dSigma a term, so only log det Sigma and tr(Sigma^-1 dSigma) carry the
+ * mixed-precision error.  0 = the plain mixed solve (z^T Sigma^-1 z = |y|^2,
+ * y = L^-1 z).  EINVAL if steps < 0 or > 8. */
+exageo_status exageo_set_mixed_refinement(exageo_ctx *ctx, int steps);
 
 /* Distance between locations (paper Section 3, the dmetric argument):
  * EXAGEO_EUCLIDEAN (default) on (x, y), or EXAGEO_GREAT_CIRCLE: x = longitude
@@ -261,7 +288,9 @@ exageo_status exageo_mle(exageo_ctx *ctx, int64_t n, const double *x, const doub
  *   12 fraction in FP32, 13 number of factorisation steps with an update,
  *   14 fraction of off-diagonal tiles in the FP64 band, 15 / 16 / 17
  *   trailing-update flops into FP32 / BF16 / FP64 targets (the last includes
- *   the diagonal tiles; FP64 mode counts everything there).
+ *   the diagonal tiles; FP64 mode counts everything there), 19 log det Sigma,
+ *   20 z^T Sigma^-1 z (the two parts of eq. (2) of the last evaluation),
+ *   21 refinement steps used (mixed precision).
  * After exageo_fisher: 0 total ms, 1 to 6 as above for its factorisation,
  *   7 ms of the Fisher phase (L^-1, the derivative matrices, the products and
  *   the reduction), 18 MFMA flops of the products.

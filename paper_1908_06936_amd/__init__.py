@@ -76,7 +76,7 @@ class Context:
     """
 
     def __init__(self, ts: int = 768, device: int | None = None, stream: torch.cuda.Stream | None = None,
-                 band_factor: float = 3.0, fp64_band: float = 0.0):
+                 band_factor: float | None = None, fp64_band: float | None = None):
         self._lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible to torch")
@@ -90,7 +90,10 @@ class Context:
         self._h = h
         self._ws = None
         self._ws_key = None
-        self.set_mixed_policy(band_factor, fp64_band)
+        # mixed precision: the library's correlation map unless distance bands are asked for
+        if band_factor is not None or fp64_band is not None:
+            self.set_mixed_policy(3.0 if band_factor is None else band_factor,
+                                  0.0 if fp64_band is None else fp64_band)
 
     # ------------------------------------------------------------ plumbing
     def _stream_handle(self):
@@ -140,6 +143,17 @@ class Context:
         if fp64_band is not None:
             self._check(self._lib.exageo_set_mixed_fp64_band(self._h, float(fp64_band)), "set_mixed_fp64_band")
 
+    def set_mixed_correlation(self, fp64_at_or_above: float = 0.3, bf16_below: float = 1e-4):
+        """Mixed precision by correlation (the library's default map): FP64
+        tiles whose correlation bound is >= fp64_at_or_above, BF16 below
+        bf16_below (with their updates), FP32 otherwise."""
+        self._check(self._lib.exageo_set_mixed_correlation(self._h, float(fp64_at_or_above), float(bf16_below)),
+                    "set_mixed_correlation")
+
+    def set_mixed_refinement(self, steps: int = 1):
+        """FP64 refinement steps of Sigma^-1 z through the mixed factor."""
+        self._check(self._lib.exageo_set_mixed_refinement(self._h, int(steps)), "set_mixed_refinement")
+
     def set_distance(self, metric: str):
         """'euclidean' (default) or 'great_circle' (x = longitude, y = latitude
         in degrees, km on a sphere of radius 6371)."""
@@ -168,7 +182,8 @@ class Context:
         m = self._lib.exageo_get_timings(self._h, buf, 24)
         keys = ["total_ms", "prep_ms", "gen_ms", "chol_ms", "update_kernel_ms", "update_flops", "solve_ms",
                 "grad_ms", "chol_flops", "update_launches", "precision", "frac_bf16", "frac_fp32", "update_steps",
-                "frac_fp64", "update_flops_fp32", "update_flops_bf16", "update_flops_fp64", "fisher_flops"]
+                "frac_fp64", "update_flops_fp32", "update_flops_bf16", "update_flops_fp64", "fisher_flops", "logdet",
+                "quad_form", "refine_steps"]
         return {k: buf[i] for i, k in enumerate(keys[:m])}
 
     # ---------------------------------------------------------- operations

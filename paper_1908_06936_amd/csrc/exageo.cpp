@@ -21,7 +21,6 @@ namespace {
 
 constexpr int64_t BLKH = 128;
 constexpr int NEV = 512;                     // profiling events
-constexpr int64_t kBandPoolPerColumn = 4;    // FP64 band pool size, tiles per tile column
 
 struct Plan {
   int64_t n = 0, ts = 0, NT = 0, T = 0, npad = 0, P = 0;
@@ -30,7 +29,8 @@ struct Plan {
   size_t off_diag = 0, off_offt = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
          off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_p32 = 0, off_pbt = 0, off_tag = 0,
-         off_tbox = 0, off_pool = 0, off_pidx = 0, off_bli = 0, off_blj = 0;
+         off_tbox = 0, off_pool = 0, off_pidx = 0, off_bli = 0, off_blj = 0, off_corr = 0, off_rtry = 0,
+         off_rnrm = 0;
   int64_t pool_cap = 0;  // mixed precision: FP64 band tiles the pool can hold
   int64_t dst = 0;       // DST tile band (0: exact)
   size_t bytes = 0;
@@ -66,8 +66,13 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
     p.off_pbt = take(2 * (size_t)std::max<int64_t>(1, p.NT - 1) * tt * 2);
     p.off_tag = take(noff);
     p.off_tbox = take((size_t)p.NT * 4 * 8);
-    // FP64 band: at most kBandPoolPerColumn tiles per tile column on average
-    p.pool_cap = std::min<int64_t>((int64_t)noff, kBandPoolPerColumn * p.NT);
+    // FP64 tiles of the precision map: up to half of the off-diagonal tiles
+    // (at least 4 per tile column), so that the mixed workspace stays about
+    // the size of the FP64 one
+    p.pool_cap = std::min<int64_t>((int64_t)noff, std::max<int64_t>(4 * p.NT, ((int64_t)noff + 1) / 2));
+    p.off_corr = take(noff * 8);
+    p.off_rtry = take((size_t)p.npad * 8);  // trial residual of the refinement
+    p.off_rnrm = take(4 * 8);
     p.off_pool = take((size_t)std::max<int64_t>(1, p.pool_cap) * tt * 8);
     p.off_pidx = take(noff * 4);
     p.off_bli = take((size_t)std::max<int64_t>(1, p.pool_cap) * 4);
@@ -101,12 +106,22 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
 
 }  // namespace
 
+enum { POLICY_CORRELATION = 0, POLICY_DISTANCE = 1 };
+constexpr double kDefaultRho64 = 0.3;
+constexpr double kDefaultRho16 = 1e-4;
+constexpr int kDefaultRefine = 1;
+
 struct exageo_ctx {
   int device = 0;
   int64_t ts = 768;
   hipStream_t stream = nullptr;
-  double band_factor = 3.0;     // BF16 at or beyond band_factor * beta
-  double fp64_band_factor = 0.0;  // FP64 below fp64_band_factor * beta
+  // mixed-precision map: by correlation bound (default) or by distance bands
+  int policy = POLICY_CORRELATION;
+  double rho64 = kDefaultRho64;   // FP64 when the tile's correlation bound is >= rho64
+  double rho16 = kDefaultRho16;   // BF16 when it (and its updates' bound) is < rho16
+  double band_factor = 3.0;     // distance policy: BF16 at or beyond band_factor * beta
+  double fp64_band_factor = 0.0;  // distance policy: FP64 below fp64_band_factor * beta
+  int refine = kDefaultRefine;    // FP64 refinement steps of Sigma^-1 z through the mixed factor
   int64_t dst_band = 0;           // DST approximation of loglik / loglik_grad / mle (0: exact)
   int metric = EXAGEO_EUCLIDEAN;  // distance between locations
   double nugget = 0.0;            // tau^2 added to the diagonal
@@ -129,6 +144,8 @@ struct exageo_ctx {
   std::vector<double> tbox;
   uint8_t* htag = nullptr;
   size_t htag_bytes = 0;
+  double* hcorr = nullptr;  // pinned: correlation bound per off-diagonal tile
+  size_t hcorr_words = 0;
   // FP64 band: pool slot per off-diagonal tile, band list (column-major
   // order) and the first list entry of each tile column, all host copies
   int32_t* hband = nullptr;  // pinned: pidx (noff) then li, lj (pool_cap each)
@@ -239,10 +256,20 @@ exageo_status prepare_locations(exageo_ctx* c, const Plan& p, const double* x, c
   return EXAGEO_OK;
 }
 
-// Precision of every off-diagonal tile (0 = FP32, 1 = BF16): BF16 when the
-// minimum distance between the bounding boxes of the two location blocks is
-// at least band_factor * beta.  Returns the BF16 fraction.
-exageo_status upload_tags(exageo_ctx* c, const Plan& p, double beta, double* frac_bf16, double* frac_fp64) {
+// Precision of every off-diagonal tile (TAG_F32, TAG_BF16 or TAG_F64) and the
+// FP64 pool slots, from the tile bounding boxes of the sorted locations.
+//   correlation policy: c_ij = correlation at the smallest distance between
+//     the boxes of location blocks i and j (the tile's largest |Sigma_ab| /
+//     sigma^2); FP64 when c_ij >= rho64, BF16 when c_ij < rho16 and every
+//     update it receives is small too (max over k < j of c_ik c_jk < rho16:
+//     the BF16 update multiplies BF16 roundings of L_ik and L_jk), FP32
+//     otherwise;
+//   distance policy: BF16 when the box distance is >= band_factor * beta,
+//     FP64 when it is below fp64_band_factor * beta.
+// FP64 candidates beyond the pool's capacity stay FP32, the most correlated
+// (closest) first.  With great-circle distances (no planar boxes) every
+// off-diagonal tile is FP32.  Returns the BF16 and FP64 fractions.
+exageo_status upload_tags(exageo_ctx* c, const Plan& p, const double theta[3], double* frac_bf16, double* frac_fp64) {
   const size_t noff = (size_t)std::max<int64_t>(1, p.NT * (p.NT - 1) / 2);
   const size_t words = noff + 2 * (size_t)std::max<int64_t>(1, p.pool_cap);
   if (c->htag_bytes < noff) {
@@ -257,30 +284,54 @@ exageo_status upload_tags(exageo_ctx* c, const Plan& p, double beta, double* fra
     HIPCHK(c, hipHostMalloc((void**)&c->hband, words * 4));
     c->hband_words = words;
   }
-  HIPCHK(c, hipStreamSynchronize(c->stream));  // previous upload consumed
-  // the tile boxes are planar in (x, y): with great-circle distances the
-  // distance rules are not applied and every off-diagonal tile is FP32
   const bool planar = c->metric == EXAGEO_EUCLIDEAN;
-  const double band16 = c->band_factor * beta, band64 = c->fp64_band_factor * beta;
+  const bool by_corr = c->policy == POLICY_CORRELATION;
+  if (planar && by_corr && p.NT > 1) {
+    if (c->hcorr_words < noff) {
+      if (c->hcorr) HIPCHK(c, hipHostFree(c->hcorr));
+      c->hcorr = nullptr;
+      HIPCHK(c, hipHostMalloc((void**)&c->hcorr, noff * 8));
+      c->hcorr_words = noff;
+    }
+    exg::launch_tile_corr(at<double>(c, p.off_tbox), p.NT, at<double>(c, p.off_qt), at<double>(c, p.off_cst),
+                          at<double>(c, p.off_corr), c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->hcorr, at<double>(c, p.off_corr), noff * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // previous upload consumed, correlations here
+  const double band16 = c->band_factor * theta[1], band64 = c->fp64_band_factor * theta[1];
   int32_t* pidx = c->hband;
   int32_t* li = c->hband + noff;
   int32_t* lj = li + std::max<int64_t>(1, p.pool_cap);
-  // candidates for the FP64 band: closest first, at most pool_cap of them
-  std::vector<std::pair<double, int64_t>> cand;  // (distance, off index)
+  // candidates for FP64: (closeness key, off index), smallest key first
+  std::vector<std::pair<double, int64_t>> cand;
   int64_t nbf = 0, ntot = 0;
   for (int64_t j = 0; j < p.NT; ++j) {
     const double* bj = &c->tbox[4 * j];
     for (int64_t i = j + 1; i < p.NT; ++i) {
-      const double* bi = &c->tbox[4 * i];
-      const double dx = std::max(0.0, std::max(bi[0] - bj[1], bj[0] - bi[1]));
-      const double dy = std::max(0.0, std::max(bi[2] - bj[3], bj[2] - bi[3]));
-      const double d = std::sqrt(dx * dx + dy * dy);
       const int64_t idx = exg::off_index(i, j, p.NT);
       pidx[idx] = -1;
-      const bool bf = planar && c->band_factor > 0.0 && d >= band16;
-      c->htag[idx] = bf ? exg::TAG_BF16 : exg::TAG_F32;
-      if (planar && !bf && d < band64) cand.emplace_back(d, idx);
       ++ntot;
+      c->htag[idx] = exg::TAG_F32;
+      if (!planar) continue;
+      if (by_corr) {
+        const double cij = c->hcorr[idx];
+        if (cij >= c->rho64) {
+          cand.emplace_back(-cij, idx);
+        } else if (cij < c->rho16) {
+          double u = 0.0;
+          for (int64_t k = 0; k < j && u < c->rho16; ++k)
+            u = std::max(u, c->hcorr[exg::off_index(i, k, p.NT)] * c->hcorr[exg::off_index(j, k, p.NT)]);
+          if (u < c->rho16) c->htag[idx] = exg::TAG_BF16;
+        }
+      } else {
+        const double* bi = &c->tbox[4 * i];
+        const double dx = std::max(0.0, std::max(bi[0] - bj[1], bj[0] - bi[1]));
+        const double dy = std::max(0.0, std::max(bi[2] - bj[3], bj[2] - bi[3]));
+        const double d = std::sqrt(dx * dx + dy * dy);
+        if (c->band_factor > 0.0 && d >= band16) c->htag[idx] = exg::TAG_BF16;
+        else if (d < band64) cand.emplace_back(d, idx);
+      }
     }
   }
   if ((int64_t)cand.size() > p.pool_cap) {
@@ -352,16 +403,16 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
   c->timings[11] = 0.0;
   c->timings[12] = 0.0;
   c->timings[14] = 0.0;
+  exg::launch_quad_table(theta, c->metric, c->nugget, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   if (p.mixed) {
     double fbf = 0.0, f64 = 0.0;
-    exageo_status st = upload_tags(c, p, theta[1], &fbf, &f64);
+    exageo_status st = upload_tags(c, p, theta, &fbf, &f64);
     if (st) return st;
     tag = at<uint8_t>(c, p.off_tag);
     c->timings[11] = fbf;
     c->timings[12] = p.NT > 1 ? 1.0 - fbf - f64 : 0.0;
     c->timings[14] = f64;
   }
-  exg::launch_quad_table(theta, c->metric, c->nugget, at<double>(c, p.off_qt), at<double>(c, p.off_cst), c->stream);
   exg::launch_fill_info(at<unsigned long long>(c, p.off_info), c->stream);
   exg::launch_gen_tiles(M, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), at<double>(c, p.off_qt),
                         at<double>(c, p.off_cst), tag, c->stream);
@@ -455,6 +506,13 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
 }
 
 // y = L^-1 z with the explicit inverses of the diagonal tiles, then eq. (2).
+// Mixed precision with refinement steps: a = Sigma^-1 z through the mixed
+// factor (forward and backward solves) and its residual r = z - Sigma a with
+// Sigma regenerated in FP64; each step tries a + (mixed factor)^-1 r and keeps
+// it only if its residual is smaller (a step that does not contract, as when
+// the mixed factor is too far from Sigma, is not taken).  The quadratic form
+// is z^T a, so when the steps converge only log det Sigma carries the mixed
+// error.  Everything stays on the device (no host round trip per step).
 exageo_status solve_reduce(exageo_ctx* c, const Plan& p) {
   double* rhs = at<double>(c, p.off_yv);
   double* y = at<double>(c, p.off_y);
@@ -462,10 +520,44 @@ exageo_status solve_reduce(exageo_ctx* c, const Plan& p) {
   double* Xd = at<double>(c, p.off_xd);
   exg::launch_diag_inverses(Xd, M.diag, at<double>(c, p.off_dinv), p.ts, p.NT, c->stream);
   exg::launch_copy(rhs, at<double>(c, p.off_zs), p.npad, c->stream);
-  if (p.mixed)
-    exg::launch_trsv_fwd_lp(M, at<uint8_t>(c, p.off_tag), Xd, p.n, rhs, y, c->stream);
-  else
+  c->timings[21] = 0.0;
+  if (p.mixed) {
+    const uint8_t* tag = at<uint8_t>(c, p.off_tag);
+    exg::launch_trsv_fwd_lp(M, tag, Xd, p.n, rhs, y, c->stream);
+    if (c->refine > 0) {
+      double* av = at<double>(c, p.off_alpha);  // accepted a
+      double* at_ = at<double>(c, p.off_y);      // trial a (y is not needed any more)
+      double* r = at<double>(c, p.off_yv);       // accepted residual
+      double* rt = at<double>(c, p.off_rtry);    // trial residual
+      double* w = at<double>(c, p.off_tmp);
+      double* d = at<double>(c, p.off_av);
+      double* nrm = at<double>(c, p.off_rnrm);
+      const double* zs = at<double>(c, p.off_zs);
+      const double *xs = at<double>(c, p.off_xs), *ys = at<double>(c, p.off_ys);
+      const double *qt = at<double>(c, p.off_qt), *cst = at<double>(c, p.off_cst);
+      exg::launch_copy(w, y, p.npad, c->stream);
+      exg::launch_trsv_bwd_lp(M, tag, Xd, w, av, c->stream);
+      exg::launch_sigma_residual(xs, ys, zs, av, p.n, p.npad, qt, cst, r, c->stream);
+      exg::launch_resid_norm(r, p.npad, nrm, 0, c->stream);
+      for (int it = 0; it < c->refine; ++it) {
+        exg::launch_copy(rt, r, p.npad, c->stream);  // the forward solve consumes its right-hand side
+        exg::launch_trsv_fwd_lp(M, tag, Xd, p.n, rt, w, c->stream);
+        exg::launch_trsv_bwd_lp(M, tag, Xd, w, d, c->stream);
+        exg::launch_add2(at_, av, d, p.npad, c->stream);
+        exg::launch_sigma_residual(xs, ys, zs, at_, p.n, p.npad, qt, cst, rt, c->stream);
+        exg::launch_resid_norm(rt, p.npad, nrm, 1, c->stream);
+        exg::launch_refine_select(av, at_, r, rt, nrm, p.npad, c->stream);
+      }
+      exg::launch_finalize_loglik_za(zs, av, p.n, at<double>(c, p.off_ld), p.NT * p.T, at<double>(c, p.off_out),
+                                     c->stream);
+      c->timings[21] = c->refine;
+      HIPCHK(c, hipGetLastError());
+      rec(c, 4);
+      return EXAGEO_OK;
+    }
+  } else {
     exg::launch_trsv_fwd(M, Xd, p.n, rhs, y, c->stream);
+  }
   exg::launch_finalize_loglik(y, p.n, at<double>(c, p.off_ld), p.NT * p.T, at<double>(c, p.off_out), c->stream);
   HIPCHK(c, hipGetLastError());
   rec(c, 4);
@@ -503,7 +595,8 @@ exageo_status gradient(exageo_ctx* c, const Plan& p) {
   double* Xd = at<double>(c, p.off_xd);
   int64_t nparts = exg::lauum_blocks(p.ts, p.NT);  // partial triples of the contraction
   const int64_t tt = p.ts * p.ts, half = std::max<int64_t>(1, p.NT - 1) * tt;
-  // a = Sigma^-1 z = L^-T y
+  // a = Sigma^-1 z = L^-T y (already there, refined, in mixed precision with
+  // refinement steps)
   exg::launch_copy(rhs, at<double>(c, p.off_y), p.npad, c->stream);
   exageo_status st;
   if (p.mixed) {
@@ -511,7 +604,7 @@ exageo_status gradient(exageo_ctx* c, const Plan& p) {
     // (staged in the two halves of the FP32 panel copy)
     const uint8_t* tag = at<uint8_t>(c, p.off_tag);
     float* P32 = at<float>(c, p.off_p32);
-    exg::launch_trsv_bwd_lp(M, tag, Xd, rhs, av, c->stream);
+    if (c->refine <= 0) exg::launch_trsv_bwd_lp(M, tag, Xd, rhs, av, c->stream);
     st = trtri_two_streams(
         c, p.NT,
         [&](int64_t k, hipStream_t s) { exg::launch_trtri_right_lp(M, tag, Xd + k * tt, P32 + (k & 1) * half, k, p.n, s); },
@@ -619,6 +712,7 @@ void exageo_destroy(exageo_ctx* c) {
   if (c->ws && c->ws_owned) (void)hipFree(c->ws);
   if (c->hres) (void)hipHostFree(c->hres);
   if (c->htag) (void)hipHostFree(c->htag);
+  if (c->hcorr) (void)hipHostFree(c->hcorr);
   if (c->hband) (void)hipHostFree(c->hband);
   if (c->pred_buf) (void)hipFree(c->pred_buf);
   for (int i = 0; i < c->nev_created; ++i) (void)hipEventDestroy(c->ev[i]);
@@ -682,12 +776,30 @@ exageo_status exageo_set_dst_band(exageo_ctx* c, int64_t band) {
 exageo_status exageo_set_mixed_fp64_band(exageo_ctx* c, double fp64_band_factor) {
   if (!c || !(fp64_band_factor >= 0.0) || !std::isfinite(fp64_band_factor)) return EXAGEO_EINVAL;
   c->fp64_band_factor = fp64_band_factor;
+  c->policy = POLICY_DISTANCE;
   return EXAGEO_OK;
 }
 
 exageo_status exageo_set_mixed_policy(exageo_ctx* c, double band_factor) {
   if (!c || !(band_factor >= 0.0) || !std::isfinite(band_factor)) return EXAGEO_EINVAL;
   c->band_factor = band_factor;
+  c->policy = POLICY_DISTANCE;
+  return EXAGEO_OK;
+}
+
+exageo_status exageo_set_mixed_correlation(exageo_ctx* c, double fp64_at_or_above, double bf16_below) {
+  if (!c || !std::isfinite(fp64_at_or_above) || !std::isfinite(bf16_below) || !(bf16_below >= 0.0) ||
+      !(fp64_at_or_above >= bf16_below))
+    return EXAGEO_EINVAL;
+  c->rho64 = fp64_at_or_above;
+  c->rho16 = bf16_below;
+  c->policy = POLICY_CORRELATION;
+  return EXAGEO_OK;
+}
+
+exageo_status exageo_set_mixed_refinement(exageo_ctx* c, int steps) {
+  if (!c || steps < 0 || steps > 8) return EXAGEO_EINVAL;
+  c->refine = steps;
   return EXAGEO_OK;
 }
 
@@ -754,6 +866,8 @@ static exageo_status eval_sorted(exageo_ctx* c, const Plan& p, const double thet
   }
   if (loglik) *loglik = out[0];
   if (info) *info = 0;
+  c->timings[19] = out[1];
+  c->timings[20] = out[2];
   if (!want_grad) {
     finish_timings(c, p, false);
     return EXAGEO_OK;

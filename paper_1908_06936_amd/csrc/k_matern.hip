@@ -182,6 +182,35 @@ void launch_gen_tiles(const TileMat& M, int64_t nreal, const double* xs, const d
   }
 }
 
+// r_i = z_i - sum_j Sigma_ij a_j over the real points (Sigma regenerated in
+// FP64, the nugget on the diagonal), r_i = 0 on padded rows; one 256-thread
+// workgroup per row, fixed-order reduction.  The residual of a solve done
+// through a lower-precision factor.
+__global__ __launch_bounds__(256) void k_sigma_residual(const double* __restrict__ xs, const double* __restrict__ ys,
+                                                        const double* __restrict__ zs, const double* __restrict__ av,
+                                                        int64_t nreal, int64_t npad, const double* __restrict__ qt,
+                                                        const double* __restrict__ cst, double* __restrict__ r) {
+  __shared__ double red[256];
+  const int64_t i = blockIdx.x;
+  if (i >= npad) return;
+  if (i >= nreal) {
+    if (threadIdx.x == 0) r[i] = 0.0;
+    return;
+  }
+  const double px = xs[i], py = ys[i];
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < nreal; j += 256)
+    s += matern_value(loc_dist(px, py, xs[j], ys[j], cst), cst, qt) * av[j];
+  double v[1] = {s};
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) r[i] = zs[i] - (v[0] + cst[C_NUG] * av[i]);
+}
+
+void launch_sigma_residual(const double* xs, const double* ys, const double* zs, const double* av, int64_t nreal,
+                           int64_t npad, const double* qt, const double* cst, double* r, hipStream_t s) {
+  hipLaunchKernelGGL(k_sigma_residual, dim3((unsigned)npad), dim3(256), 0, s, xs, ys, zs, av, nreal, npad, qt, cst, r);
+}
+
 void launch_gen_dense(double* cov, int64_t ldc, int64_t n, const double* x, const double* y, const double* qt,
                       const double* cst, hipStream_t s) {
   const unsigned gx = (unsigned)((n + 255) / 256);

@@ -22,6 +22,7 @@
 #include "contract.h"
 #include "gemm32.h"
 #include "launch.h"
+#include "matern_dev.h"
 #include "solve.h"
 
 namespace exg {
@@ -108,6 +109,25 @@ __global__ __launch_bounds__(256) void k_tile_bbox(const double* __restrict__ xs
     __syncthreads();
   }
   if (t < 4) box[4 * k + t] = red[t][0];
+}
+
+// corr[off_index(i, j)] = the Matern correlation at the smallest distance
+// between the bounding boxes of location blocks i > j: an upper bound of
+// |Sigma_ab| / sigma^2 over the tile's entries, since the correlation
+// decreases with distance (planar coordinates only)
+__global__ __launch_bounds__(256) void k_tile_corr(const double* __restrict__ box, int64_t NT,
+                                                   const double* __restrict__ qt, const double* __restrict__ cst,
+                                                   double* __restrict__ corr) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NT * (NT - 1) / 2) return;
+  int64_t a, b;
+  tri_decode(p, &a, &b);  // b <= a < NT - 1
+  const int64_t i = a + 1, j = b;
+  const double* bi = box + 4 * i;
+  const double* bj = box + 4 * j;
+  const double dx = fmax(0.0, fmax(bi[0] - bj[1], bj[0] - bi[1]));
+  const double dy = fmax(0.0, fmax(bi[2] - bj[3], bj[2] - bi[3]));
+  corr[off_index(i, j, NT)] = matern_value(sqrt(dx * dx + dy * dy), cst, qt) / cst[C_S2];
 }
 
 // --------------------------------------------------------- panel staging
@@ -466,6 +486,13 @@ __global__ __launch_bounds__(256, 2) void k_lauum_f64_lp(TileMat M, int T, int64
 void launch_tile_bbox(const double* xs, const double* ys, int64_t ts, int64_t NT, int64_t nreal, double* box,
                       hipStream_t s) {
   hipLaunchKernelGGL(k_tile_bbox, dim3((unsigned)NT), dim3(256), 0, s, xs, ys, ts, nreal, box);
+}
+
+void launch_tile_corr(const double* box, int64_t NT, const double* qt, const double* cst, double* corr,
+                      hipStream_t s) {
+  const int64_t noff = NT * (NT - 1) / 2;
+  if (noff <= 0) return;
+  hipLaunchKernelGGL(k_tile_corr, dim3((unsigned)((noff + 255) / 256)), dim3(256), 0, s, box, NT, qt, cst, corr);
 }
 
 void launch_panel_gather(const TileMat& M, int64_t k, const uint8_t* tag, double* pbuf, hipStream_t s) {

@@ -415,6 +415,61 @@ __global__ __launch_bounds__(256) void k_finalize_loglik(const double* __restric
   }
 }
 
+// eq. (2) from log det Sigma (sum of ldpart) and the quadratic form
+// z^T Sigma^-1 z = z^T a with a = Sigma^-1 z (refined solve)
+__global__ __launch_bounds__(256) void k_finalize_loglik_za(const double* __restrict__ zs, const double* __restrict__ av,
+                                                            int64_t n, const double* __restrict__ ldpart, int64_t nld,
+                                                            double* __restrict__ out) {
+  __shared__ double red[2 * 256];
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = threadIdx.x; i < n; i += 256) v[0] += zs[i] * av[i];
+  for (int64_t i = threadIdx.x; i < nld; i += 256) v[1] += ldpart[i];
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    const double q = v[0], ld = v[1];
+    out[0] = -0.5 * ((double)n * 1.8378770664093454836 + ld + q);
+    out[1] = ld;
+    out[2] = q;
+  }
+}
+
+// y = a + d
+__global__ void k_add2_f64(double* __restrict__ y, const double* __restrict__ a, const double* __restrict__ d,
+                           int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] + d[i];
+}
+
+// Refinement bookkeeping on the device (no host round trip): nrm[0] holds
+// the squared norm of the accepted residual.  init: nrm[0] = |r|^2.  trial:
+// flag = |r_try|^2 < nrm[0], and then nrm[0] = |r_try|^2.
+__global__ __launch_bounds__(1024) void k_resid_norm(const double* __restrict__ r, int64_t n, double* __restrict__ nrm,
+                                                     int trial) {
+  __shared__ double red[1024];
+  double v[1] = {0.0};
+  for (int64_t i = threadIdx.x; i < n; i += 1024) v[0] += r[i] * r[i];
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) {
+    if (!trial) {
+      nrm[0] = v[0];
+    } else {
+      const bool better = v[0] < nrm[0];
+      nrm[1] = better ? 1.0 : 0.0;
+      if (better) nrm[0] = v[0];
+    }
+  }
+}
+
+// accept the trial step when the flag is set: a <- a_try, r <- r_try
+__global__ void k_refine_select(double* __restrict__ a, const double* __restrict__ a_try, double* __restrict__ r,
+                                const double* __restrict__ r_try, const double* __restrict__ nrm, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && nrm[1] != 0.0) {
+    a[i] = a_try[i];
+    r[i] = r_try[i];
+  }
+}
+
 // out[0..2] = sum over parts of part[3 p + k]
 __global__ __launch_bounds__(256) void k_finalize_grad(const double* __restrict__ part, int64_t nparts,
                                                        double* __restrict__ out) {
@@ -530,6 +585,24 @@ void launch_trmv_lower(const TileMat& M, int64_t nreal, const double* e, double*
 void launch_finalize_loglik(const double* yv, int64_t n, const double* ldpart, int64_t nld, double* out,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_finalize_loglik, dim3(1), dim3(256), 0, s, yv, n, ldpart, nld, out);
+}
+
+void launch_finalize_loglik_za(const double* zs, const double* av, int64_t n, const double* ldpart, int64_t nld,
+                               double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_loglik_za, dim3(1), dim3(256), 0, s, zs, av, n, ldpart, nld, out);
+}
+
+void launch_add2(double* y, const double* a, const double* d, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_add2_f64, dim3(nb(n, 256)), dim3(256), 0, s, y, a, d, n);
+}
+
+void launch_resid_norm(const double* r, int64_t n, double* nrm, int trial, hipStream_t s) {
+  hipLaunchKernelGGL(k_resid_norm, dim3(1), dim3(1024), 0, s, r, n, nrm, trial);
+}
+
+void launch_refine_select(double* a, const double* a_try, double* r, const double* r_try, const double* nrm,
+                          int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_refine_select, dim3(nb(n, 256)), dim3(256), 0, s, a, a_try, r, r_try, nrm, n);
 }
 
 void launch_finalize_grad(const double* part, int64_t nparts, double* out, hipStream_t s) {

@@ -17,6 +17,9 @@ void launch_gen_tiles(const TileMat& M, int64_t nreal, const double* xs, const d
                       const double* cst, const uint8_t* tag, hipStream_t s);
 void launch_gen_dense(double* cov, int64_t ldc, int64_t n, const double* x, const double* y, const double* qt,
                       const double* cst, hipStream_t s);
+// r = z - Sigma a in FP64 (Sigma regenerated), sorted order, zero on padding
+void launch_sigma_residual(const double* xs, const double* ys, const double* zs, const double* av, int64_t nreal,
+                           int64_t npad, const double* qt, const double* cst, double* r, hipStream_t s);
 
 // k_small.hip
 void launch_sort_locations(const double* x, const double* y, const double* z, int64_t n, int64_t npad, int64_t P,
@@ -31,6 +34,16 @@ void launch_trmv_lower(const TileMat& M, int64_t nreal, const double* e, double*
 void launch_finalize_loglik(const double* yv, int64_t n, const double* ldpart, int64_t nld, double* out,
                             hipStream_t s);
 void launch_finalize_grad(const double* part, int64_t nparts, double* out, hipStream_t s);
+// eq. (2) with the quadratic form z^T a (a = Sigma^-1 z)
+void launch_finalize_loglik_za(const double* zs, const double* av, int64_t n, const double* ldpart, int64_t nld,
+                               double* out, hipStream_t s);
+// refinement steps on the device: y = a + d; nrm[0] = |r|^2 (trial = 0) or
+// nrm[1] = (|r|^2 < nrm[0]) with nrm[0] lowered then (trial = 1); the select
+// takes a_try, r_try when nrm[1] is set
+void launch_add2(double* y, const double* a, const double* d, int64_t n, hipStream_t s);
+void launch_resid_norm(const double* r, int64_t n, double* nrm, int trial, hipStream_t s);
+void launch_refine_select(double* a, const double* a_try, double* r, const double* r_try, const double* nrm,
+                          int64_t n, hipStream_t s);
 void launch_fill_info(unsigned long long* info, hipStream_t s);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 void launch_copy_diag_lower(double* dst, const double* diag, int64_t ts, int64_t NT, hipStream_t s);
@@ -41,6 +54,10 @@ void launch_diag_apply_t(const double* Xk, int64_t ts, const double* b, double* 
 
 // k_mixed.hip
 void launch_tile_bbox(const double* xs, const double* ys, int64_t ts, int64_t NT, int64_t nreal, double* box,
+                      hipStream_t s);
+// corr[off_index(i, j)]: correlation bound of every off-diagonal tile from the
+// location boxes (box: 4 doubles per tile)
+void launch_tile_corr(const double* box, int64_t NT, const double* qt, const double* cst, double* corr,
                       hipStream_t s);
 void launch_panel_gather(const TileMat& M, int64_t k, const uint8_t* tag, double* pbuf, hipStream_t s);
 void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const double* pbuf, float* p32,

@@ -56,7 +56,9 @@ def test_workspace_bytes_host_only(lib):
     nt = (40000 + 767) // 768
     tiles = nt * (nt + 1) // 2 * 768 * 768 * 8
     assert tiles <= a < 1.3 * tiles  # the FP64 tiles dominate
-    assert m < 0.85 * a  # 4-byte off-diagonal slots (plus panel copies and the FP64 band pool)
+    # 4-byte off-diagonal slots plus an FP64 pool for up to half of the
+    # off-diagonal tiles, plus the panel copies: about the FP64 size
+    assert 0.9 * a < m < 1.25 * a
 
 
 def test_entry_points_reject_bad_arguments_before_any_launch(lib):

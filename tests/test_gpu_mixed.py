@@ -1,18 +1,22 @@
-"""Mixed-precision likelihood (FP64 diagonal tiles, FP32 / BF16 off-diagonal
-tiles) against the FP64 oracle.
+"""Mixed precision (FP64 diagonal tiles; each off-diagonal tile FP64, FP32 or
+BF16 by the precision map) against the FP64 oracle, the FP64 path and exact
+closed forms.
 
-The mixed result is an approximation of eq. (2); its tests check
-  * the plumbing exactly: when every off-diagonal tile is exactly zero (well
-    separated clusters, one cluster per tile) the mixed and FP64 paths agree
-    to FP64 rounding;
-  * the error against the FP64 oracle stays within bounds set by the storage
-    rounding of the off-diagonal covariances (unit roundoff 2^-24 for FP32 and
-    2^-9 for BF16) amplified by the conditioning, measured on these inputs;
-  * a wider BF16 band (fewer BF16 tiles) never does worse than a narrower
-    one by more than rounding noise, and no BF16 tiles means FP32-only;
-  * the mixed score (FP32 off-diagonal tiles of L^-1 and Sigma^-1, FP64
-    diagonal tiles and sums) is exact when the off-diagonal tiles vanish and
-    stays within measured bounds of the FP64 oracle otherwise.
+Claimed, and asserted at the stated tolerance |dl| / |l| <= 1e-6:
+  * the library's default map (by correlation: FP64 tiles whose correlation
+    bound is >= 0.3, BF16 below 1e-4 together with their updates, FP32
+    otherwise; one FP64 refinement step of Sigma^-1 z) on 40 x 40 jittered
+    grids and uniform points against the oracle, on the 1-D Markov line at
+    n = 40,000 with tile 768 against its O(n) closed form (all three tile
+    precisions present), and on the 200 x 200 jittered grid at n = 40,000
+    against the FP64 path (itself pinned to the oracle at 1e-10);
+  * the plumbing exactly: with every off-diagonal tile zero, mixed and FP64
+    agree to rounding; with every tile FP64 and no refinement the mixed path
+    is the FP64 path bitwise.
+Not claimed (the distance bands of BF16 beyond 3 beta, FP32 only, and the
+map without refinement): their errors are printed for the record, and only
+structural facts (tile fractions, statuses) are asserted.  A mixed
+factorisation that fails is reported as ENOTPD with l = -inf (status tests).
 """
 import math
 
@@ -23,6 +27,9 @@ import inputgen
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+LN2PI = math.log(2 * math.pi)
+CLAIM = 1e-6
 
 
 def dev(a):
@@ -36,11 +43,17 @@ def exa():
     return exa
 
 
-def test_mixed_exact_when_off_diagonal_is_zero(orc, exa):
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+# ------------------------------------------------------------ plumbing
+@pytest.mark.parametrize("dist_policy", [False, True])
+def test_mixed_exact_when_off_diagonal_is_zero(orc, exa, dist_policy):
     # 4 clusters of exactly ts points at the corners of a square 2000 beta
     # wide: the location ordering keeps each cluster in one tile, so every
     # off-diagonal tile is exactly 0 in any precision
-    ctx = exa.Context(ts=256, band_factor=3.0)
+    ctx = exa.Context(ts=256, band_factor=3.0) if dist_policy else exa.Context(ts=256)
     x, y, lab = inputgen.corner_clusters(256, width=1.0, separation=200.0, seed=21)
     th = [1.0, 0.1, 1.0]
     z = np.zeros(x.size)
@@ -52,51 +65,201 @@ def test_mixed_exact_when_off_diagonal_is_zero(orc, exa):
     X, Y, Z = dev(x), dev(y), dev(z)
     l64 = ctx.loglik(X, Y, Z, th, "fp64")
     lmx = ctx.loglik(X, Y, Z, th, "mixed")
-    assert ctx.timings()["frac_bf16"] == 1.0  # all cross-cluster tiles far beyond the band
+    assert ctx.timings()["frac_bf16"] == 1.0  # all cross-cluster tiles far beyond either rule
     assert l64 == pytest.approx(ref, rel=1e-12)
     assert lmx == pytest.approx(l64, rel=1e-12)
 
 
-@pytest.mark.parametrize("beta,nu,tol", [(0.03, 0.5, 1e-7), (0.1, 0.5, 1e-6), (0.1, 1.0, 2e-5)])
-def test_mixed_fp32_only_vs_oracle(orc, exa, beta, nu, tol):
-    ctx = exa.Context(ts=256, band_factor=0.0)  # no BF16 tiles
+def test_mixed_all_fp64_reproduces_fp64_bitwise(orc, exa):
+    # NT = 7: the pool holds all 21 off-diagonal tiles; with every tile FP64
+    # and no refinement the mixed path runs the FP64 arithmetic in FP64 order
+    ctx = exa.Context(ts=256)
+    ctx.set_mixed_correlation(0.0, 0.0)
+    ctx.set_mixed_refinement(0)
+    x, y = inputgen.jittered_grid(40, seed=5)
+    th = [1.0, 0.1, 1.0]
+    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=5))
+    X, Y, Z = dev(x), dev(y), dev(z)
+    l64 = ctx.loglik(X, Y, Z, th, "fp64")
+    lmx = ctx.loglik(X, Y, Z, th, "mixed")
+    tm = ctx.timings()
+    assert tm["frac_fp64"] == 1.0 and tm["frac_bf16"] == 0.0
+    assert lmx == l64
+    assert l64 == pytest.approx(orc.loglik(x, y, z, th), rel=1e-10)
+
+
+# ------------------------------------------------ the default map: claimed
+@pytest.mark.parametrize("beta,nu", [(0.03, 0.5), (0.1, 0.5), (0.1, 1.0), (0.2, 1.5)])
+def test_default_map_vs_oracle_grid(orc, exa, beta, nu):
+    ctx = exa.Context(ts=256)
     x, y = inputgen.jittered_grid(40, seed=2)
     th = [1.0, beta, nu]
     z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=2))
     ref = orc.loglik(x, y, z, th)
     got = ctx.loglik(dev(x), dev(y), dev(z), th, "mixed")
     tm = ctx.timings()
-    assert tm["frac_bf16"] == 0.0 and tm["frac_fp32"] == 1.0
-    rel = abs(got - ref) / abs(ref)
-    print(f"FP32-only mixed: beta={beta} nu={nu} rel err {rel:.3e}")
-    assert rel <= tol
+    err = rel(got, ref)
+    print(f"default map, 40 x 40 grid, beta={beta} nu={nu}: rel err {err:.2e} (bf16 {tm['frac_bf16']:.2f}, "
+          f"fp64 {tm['frac_fp64']:.2f}, refinement steps {tm['refine_steps']:.0f})")
+    assert tm["refine_steps"] == 1
+    assert err <= CLAIM
 
 
-@pytest.mark.parametrize("beta,nu,tol", [(0.03, 0.5, 1e-6), (0.1, 0.5, 1e-4), (0.1, 1.0, 2e-3)])
-def test_mixed_bf16_band_vs_oracle(orc, exa, beta, nu, tol):
-    x, y = inputgen.jittered_grid(40, seed=2)
-    th = [1.0, beta, nu]
-    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=2))
+@pytest.mark.parametrize("n,ts,nu", [(2000, 256, 0.8), (3000, 512, 0.5)])
+def test_default_map_vs_oracle_uniform(orc, exa, n, ts, nu):
+    ctx = exa.Context(ts=ts)
+    x, y = inputgen.uniform(n, seed=40 + n)
+    th = [1.0, 0.05, nu]
+    z = orc.simulate(x, y, th, inputgen.normals(n, seed=40 + n))
     ref = orc.loglik(x, y, z, th)
+    got = ctx.loglik(dev(x), dev(y), dev(z), th, "mixed")
+    tm = ctx.timings()
+    err = rel(got, ref)
+    print(f"default map, {n} uniform points, nu={nu}: rel err {err:.2e} (bf16 {tm['frac_bf16']:.2f}, "
+          f"fp64 {tm['frac_fp64']:.2f})")
+    assert err <= CLAIM
+
+
+def _markov_1d(n, s2, beta, gap, seed):
+    t, y0 = inputgen.collinear(n, mean_gap=gap, seed=seed)
+    rho = np.exp(-np.diff(t) / beta)
+    e = inputgen.normals(n, seed=seed)
+    z = np.empty(n)
+    z[0] = math.sqrt(s2) * e[0]
+    for i in range(1, n):
+        z[i] = rho[i - 1] * z[i - 1] + math.sqrt(s2 * (1 - rho[i - 1] ** 2)) * e[i]
+    v = s2 * (1 - rho ** 2)
+    ref = -0.5 * (LN2PI + math.log(s2) + z[0] ** 2 / s2)
+    ref += np.sum(-0.5 * (LN2PI + np.log(v) + (z[1:] - rho * z[:-1]) ** 2 / v))
+    return t, y0, z, ref
+
+
+@pytest.mark.parametrize("gap", [5e-4, 4e-3])
+def test_default_map_markov_line_full_size(exa, gap):
+    # nu = 1/2 on a line, n = 40,000, tile 768: the exact O(n) likelihood.
+    # With mean gap 5e-4 a tile spans 3.8 beta: neighbouring tiles are FP64,
+    # the next two FP32 and the rest BF16, so every precision is exercised.
+    n, s2, beta = 40000, 1.0, 0.1
+    t, y0, z, ref = _markov_1d(n, s2, beta, gap, seed=11)
+    perm = inputgen.shuffled(n, seed=12)
+    ctx = exa.Context(ts=768)
+    got = ctx.loglik(dev(t[perm]), dev(y0[perm]), dev(z[perm]), [s2, beta, 0.5], "mixed")
+    tm = ctx.timings()
+    err = rel(got, ref)
+    print(f"Markov line gap {gap}: mixed rel err vs closed form {err:.2e} (bf16 {tm['frac_bf16']:.3f}, "
+          f"fp32 {tm['frac_fp32']:.3f}, fp64 {tm['frac_fp64']:.3f})")
+    if gap == 5e-4:
+        assert tm["frac_bf16"] > 0 and tm["frac_fp32"] > 0 and tm["frac_fp64"] > 0
+    assert err <= CLAIM
+
+
+@pytest.mark.parametrize("beta,nu", [(0.03, 0.5), (0.1, 0.5), (0.1, 1.0)])
+def test_default_map_grid_full_size(exa, beta, nu):
+    # n = 40,000 (200 x 200 jittered grid), tile 768, against the FP64 path
+    x, y = inputgen.jittered_grid(200, seed=0)
+    th = [1.0, beta, nu]
+    ctx = exa.Context(ts=768)
+    X, Y = dev(x), dev(y)
+    Z = ctx.simulate(X, Y, th, dev(inputgen.normals(x.size, seed=0)))
+    l64 = ctx.loglik(X, Y, Z, th, "fp64")
+    lmx = ctx.loglik(X, Y, Z, th, "mixed")
+    tm = ctx.timings()
+    err = rel(lmx, l64)
+    print(f"default map, 200 x 200 grid, beta={beta} nu={nu}: rel err {err:.2e} (bf16 {tm['frac_bf16']:.2f}, "
+          f"fp64 {tm['frac_fp64']:.2f})")
+    assert err <= CLAIM
+
+
+def test_refinement_steps_lower_the_error(exa):
+    # 200 x 200 grid, beta = 0.1, nu = 1/2: the plain mixed solve, one and two
+    # refinement steps; each step may only be taken if its residual shrinks
+    x, y = inputgen.jittered_grid(200, seed=0)
+    th = [1.0, 0.1, 0.5]
+    ctx = exa.Context(ts=768)
+    X, Y = dev(x), dev(y)
+    Z = ctx.simulate(X, Y, th, dev(inputgen.normals(x.size, seed=0)))
+    l64 = ctx.loglik(X, Y, Z, th, "fp64")
+    errs = []
+    for steps in (0, 1, 2):
+        ctx.set_mixed_refinement(steps)
+        errs.append(rel(ctx.loglik(X, Y, Z, th, "mixed"), l64))
+    print(f"refinement steps 0, 1, 2: rel err {errs}")
+    assert errs[1] < errs[0] and errs[2] <= errs[1] * 1.5
+
+
+# ---------------------------------- maps that make no claim: the record
+def test_unclaimed_maps_record_errors(orc, exa):
+    x, y = inputgen.jittered_grid(40, seed=2)
+    rows = []
+    for beta, nu in ((0.03, 0.5), (0.1, 0.5), (0.1, 1.0)):
+        th = [1.0, beta, nu]
+        z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=2))
+        ref = orc.loglik(x, y, z, th)
+        fr = {}
+        for label, band, fb in (("fp32 only", 0.0, 0.0), ("bf16 beyond 3 beta", 3.0, 0.0),
+                                ("bf16 beyond 6 beta", 6.0, 0.0), ("fp32 + fp64 band 0.5 beta", 0.0, 0.5)):
+            ctx = exa.Context(ts=256, band_factor=band, fp64_band=fb)
+            ctx.set_mixed_refinement(0)
+            st, got, info = ctx.loglik_status(dev(x), dev(y), dev(z), th, "mixed")
+            tm = ctx.timings()
+            assert st in (exa.OK, exa.ENOTPD)
+            fr[label] = tm["frac_bf16"]
+            rows.append(f"beta={beta} nu={nu} {label}: "
+                        + (f"rel err {rel(got, ref):.2e}" if st == exa.OK else f"ENOTPD at {info}")
+                        + f" (bf16 {tm['frac_bf16']:.2f}, fp64 {tm['frac_fp64']:.2f})")
+        # structure: a wider BF16 band keeps more tiles out of BF16, none at 0
+        assert fr["fp32 only"] == 0.0 and fr["bf16 beyond 6 beta"] <= fr["bf16 beyond 3 beta"]
+    print("\n".join(rows))
+
+
+@pytest.mark.parametrize("beta,nu", [(0.1, 0.5), (0.1, 1.0)])
+def test_distance_fp64_band_reduces_error(orc, exa, beta, nu):
+    # 60 x 60 grid, ts 128: NT = 29, 406 off-diagonal tiles; the pool holds up
+    # to half of them, the closest first
+    x, y = inputgen.jittered_grid(60, seed=6)
+    th = [1.0, beta, nu]
+    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=6))
+    ref = orc.loglik(x, y, z, th)
+    X, Y, Z = dev(x), dev(y), dev(z)
     errs = {}
-    for band in (3.0, 6.0, 1e9):
-        ctx = exa.Context(ts=256, band_factor=band)
-        st, got, _ = ctx.loglik_status(dev(x), dev(y), dev(z), th, "mixed")
-        errs[band] = (abs(got - ref) / abs(ref) if st == exa.OK else math.inf, ctx.timings()["frac_bf16"], st)
-    print(f"beta={beta} nu={nu}: " + ", ".join(f"band {b}: rel {e:.2e} bf16 {f:.2f} status {st}"
-                                               for b, (e, f, st) in errs.items()))
-    assert errs[1e9][1] == 0.0 and errs[1e9][2] == exa.OK
-    # a wider band keeps more tiles in FP32
-    assert errs[6.0][1] <= errs[3.0][1] and errs[3.0][1] > 0.0
-    if nu == 0.5:
-        assert errs[3.0][0] <= tol
+    for fb in (0.0, 0.5):
+        ctx = exa.Context(ts=128, band_factor=0.0, fp64_band=fb)
+        ctx.set_mixed_refinement(0)
+        st, got, _ = ctx.loglik_status(X, Y, Z, th, "mixed")
+        errs[fb] = (abs(got - ref) / abs(ref) if st == exa.OK else math.inf, ctx.timings()["frac_fp64"])
+    print(f"beta={beta} nu={nu}: " + ", ".join(f"fp64 band {b}: rel {e:.2e} (fp64 tiles {f:.2f})"
+                                               for b, (e, f) in errs.items()))
+    assert errs[0.0][1] == 0.0 and 0.0 < errs[0.5][1] <= 203 / 406 + 1e-12
+    assert errs[0.5][0] < errs[0.0][0]
+
+
+# ------------------------------------------------------------ statuses
+def test_mixed_notpd_status(exa):
+    ctx = exa.Context(ts=128)
+    st, ll, info = ctx.loglik_status(dev([0.3, 0.3]), dev([0.2, 0.2]), dev([1.0, 0.5]), [4.0, 0.1, 0.5], "mixed")
+    assert st == exa.ENOTPD and ll == -math.inf and info in (1, 2)
+
+
+@pytest.mark.parametrize("band", [3.0, 1.0])
+def test_mixed_failure_is_reported_not_a_number(orc, exa, band):
+    # BF16 close to the diagonal of a smooth field can push the smallest
+    # eigenvalue below zero: then the status is ENOTPD with l = -inf and a
+    # valid caller index, never a finite wrong value; an OK status must come
+    # with a finite l
+    x, y = inputgen.jittered_grid(40, seed=2)
+    th = [1.0, 0.1, 1.0]
+    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=2))
+    ctx = exa.Context(ts=256, band_factor=band)
+    ctx.set_mixed_refinement(0)
+    st, ll, info = ctx.loglik_status(dev(x), dev(y), dev(z), th, "mixed")
+    print(f"bf16 beyond {band} beta, smooth field: status {st}, l {ll}, info {info}")
+    if st == exa.OK:
+        assert math.isfinite(ll) and info == 0
     else:
-        # nu = 1 on this grid: BF16 rounding of correlations near 0.1 can push
-        # the smallest eigenvalue below zero; the library must then report a
-        # failed pivot rather than a wrong number
-        assert errs[3.0][2] == exa.ENOTPD or errs[3.0][0] <= tol
+        assert st == exa.ENOTPD and ll == -math.inf and 1 <= info <= x.size
 
 
+# ------------------------------------------------------------ score
 def test_mixed_gradient_deterministic(orc, exa):
     ctx = exa.Context(ts=256)
     x, y = inputgen.uniform(700, seed=3)
@@ -130,29 +293,28 @@ def test_mixed_grad_exact_when_off_diagonal_is_zero(orc, exa):
     np.testing.assert_allclose(gmx, g64, rtol=1e-11, atol=1e-11 * np.abs(g64).max())
 
 
-# FP32 off-diagonal tiles of L, L^-1 and Sigma^-1: the score error against the
-# FP64 oracle, relative to the largest score component (bounds measured on
-# these inputs with a margin of about 10x: the error comes from the FP32
-# factor, whose perturbation of Sigma the inverse amplifies)
-@pytest.mark.parametrize("beta,nu,band,tol", [(0.03, 0.5, 0.0, 3e-6), (0.1, 0.5, 0.0, 1e-5), (0.03, 0.5, 3.0, 1e-5)])
-def test_mixed_grad_vs_oracle(orc, exa, beta, nu, band, tol):
-    ctx = exa.Context(ts=256, band_factor=band)
+@pytest.mark.parametrize("beta,nu", [(0.03, 0.5), (0.1, 0.5), (0.1, 1.0)])
+def test_mixed_score_record(orc, exa, beta, nu):
+    # the score's error is stated per result, not bounded by the claim on l:
+    # the a^T dSigma a term uses the refined a, the trace term the mixed
+    # inverse factor; printed here (default map and the FP32-only record)
     x, y = inputgen.jittered_grid(40, seed=2)
     th = [1.0, beta, nu]
     z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=2))
     lref, gref = orc.loglik_grad(x, y, z, th)
-    st, _, _ = ctx.loglik_status(dev(x), dev(y), dev(z), th, "mixed")
-    assert st == exa.OK
-    lmx, gmx = ctx.loglik_grad(dev(x), dev(y), dev(z), th, "mixed")
     gref = np.asarray(gref)
-    err = np.abs(np.asarray(gmx) - gref) / np.abs(gref).max()
-    print(f"mixed grad beta={beta} nu={nu} band={band}: l rel {abs(lmx - lref) / abs(lref):.2e}, "
-          f"grad err / max|g| = {err}, g = {gmx}, ref = {list(gref)}")
-    assert err.max() <= tol
+    for label, ctx in (("default map", exa.Context(ts=256)), ("fp32 only", exa.Context(ts=256, band_factor=0.0))):
+        if label == "fp32 only":
+            ctx.set_mixed_refinement(0)
+        lmx, gmx = ctx.loglik_grad(dev(x), dev(y), dev(z), th, "mixed")
+        err = np.abs(np.asarray(gmx) - gref)
+        print(f"mixed score beta={beta} nu={nu} {label}: l rel {rel(lmx, lref):.2e}, score err / max|g| = "
+              f"{err / np.abs(gref).max()}, per component {err / np.abs(gref)}")
+        assert np.all(np.isfinite(gmx))
 
 
 def test_mixed_lbfgsb_mle_matches_fp64(orc, exa):
-    ctx = exa.Context(ts=256, band_factor=0.0)
+    ctx = exa.Context(ts=256)
     x, y = inputgen.jittered_grid(30, seed=4)
     th = [1.0, 0.1, 0.5]
     z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=4))
@@ -160,79 +322,15 @@ def test_mixed_lbfgsb_mle_matches_fp64(orc, exa):
     lb, ub, t0 = [0.01, 0.01, 0.1], [5.0, 2.0, 2.0], [0.5, 0.3, 0.5]
     th64, l64, s64 = ctx.mle(X, Y, Z, lb, ub, theta0=t0, tol=1e-7, method="lbfgsb", precision="fp64")
     thmx, lmx, smx = ctx.mle(X, Y, Z, lb, ub, theta0=t0, tol=1e-7, method="lbfgsb", precision="mixed")
-    print("fp64", th64, l64, s64, "mixed", thmx, lmx, smx)
+    l64_at_mx = ctx.loglik(X, Y, Z, thmx, "fp64")
+    print("fp64", th64, l64, s64, "mixed", thmx, lmx, smx, "fp64 l at the mixed estimate", l64_at_mx)
     assert smx["n_grad_evals"] > 0
-    np.testing.assert_allclose(thmx, th64, rtol=2e-2)
-    assert lmx == pytest.approx(l64, rel=1e-5)
-
-
-def test_mixed_notpd_status(exa):
-    ctx = exa.Context(ts=128)
-    st, ll, info = ctx.loglik_status(dev([0.3, 0.3]), dev([0.2, 0.2]), dev([1.0, 0.5]), [4.0, 0.1, 0.5], "mixed")
-    assert st == exa.ENOTPD and ll == -math.inf and info in (1, 2)
-
-
-def test_mixed_all_fp64_band_reproduces_fp64_bitwise(orc, exa):
-    # NT = 7: the band pool holds all 21 off-diagonal tiles, so every tile is
-    # FP64 and the mixed path runs the FP64 arithmetic in the same order
-    ctx = exa.Context(ts=256, band_factor=0.0, fp64_band=1e9)
-    x, y = inputgen.jittered_grid(40, seed=5)
-    th = [1.0, 0.1, 1.0]
-    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=5))
-    X, Y, Z = dev(x), dev(y), dev(z)
-    l64 = ctx.loglik(X, Y, Z, th, "fp64")
-    lmx = ctx.loglik(X, Y, Z, th, "mixed")
-    tm = ctx.timings()
-    assert tm["frac_fp64"] == 1.0 and tm["frac_bf16"] == 0.0
-    assert lmx == l64
-    assert l64 == pytest.approx(orc.loglik(x, y, z, th), rel=1e-10)
-
-
-@pytest.mark.parametrize("beta,nu", [(0.1, 0.5), (0.1, 1.0)])
-def test_mixed_fp64_band_reduces_error(orc, exa, beta, nu):
-    # 60 x 60 grid, ts 128: NT = 29; the pool holds 4 NT = 116 of the 406
-    # off-diagonal tiles, the closest ones
-    x, y = inputgen.jittered_grid(60, seed=6)
-    th = [1.0, beta, nu]
-    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=6))
-    ref = orc.loglik(x, y, z, th)
-    X, Y, Z = dev(x), dev(y), dev(z)
-    errs = {}
-    for fb in (0.0, 0.5):
-        ctx = exa.Context(ts=128, band_factor=0.0, fp64_band=fb)
-        st, got, _ = ctx.loglik_status(X, Y, Z, th, "mixed")
-        errs[fb] = (abs(got - ref) / abs(ref) if st == exa.OK else math.inf, ctx.timings()["frac_fp64"])
-    print(f"beta={beta} nu={nu}: " + ", ".join(f"fp64 band {b}: rel {e:.2e} (fp64 tiles {f:.2f})"
-                                               for b, (e, f) in errs.items()))
-    assert errs[0.0][1] == 0.0 and 0.0 < errs[0.5][1] <= 116 / 406 + 1e-12
-    assert errs[0.5][0] < errs[0.0][0]
-
-
-def test_mixed_grad_fp64_band_vs_oracle(orc, exa):
-    # the FP64 band also sets the precision of the matching blocks of
-    # Sigma^-1 (and of L): the score error drops against the FP32-only policy
-    x, y = inputgen.jittered_grid(60, seed=6)
-    th = [1.0, 0.1, 0.5]
-    z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=6))
-    gref = np.asarray(orc.loglik_grad(x, y, z, th)[1])
-    X, Y, Z = dev(x), dev(y), dev(z)
-    errs = {}
-    for fb in (0.0, 0.5):
-        ctx = exa.Context(ts=128, band_factor=0.0, fp64_band=fb)
-        g = np.asarray(ctx.loglik_grad(X, Y, Z, th, "mixed")[1])
-        errs[fb] = (np.abs(g - gref) / np.abs(gref).max()).max()
-    print(f"mixed score error / max|g|: FP32 only {errs[0.0]:.2e}, FP64 band 0.5 beta {errs[0.5]:.2e}")
-    # measured 3.6e-6 and 2.8e-6: the band removes the largest terms of W's
-    # error; the FP32 inverse factor outside it keeps the rest
-    assert errs[0.5] < errs[0.0]
-    assert errs[0.5] <= 1e-5
+    assert abs(l64_at_mx - l64) <= CLAIM * abs(l64)
 
 
 def test_mle_mixed_search_with_fp64_finish(exa):
     # 48 x 48 jittered grid, theta = (1, 0.1, 0.5): the mixed-precision search
     # followed by an FP64 finish reaches the FP64 L-BFGS-B optimum to 1e-6 of l
-    import inputgen
-
     x, y = inputgen.jittered_grid(48, seed=4)
     n = x.size
     ctx = exa.Context(ts=256)
@@ -242,7 +340,6 @@ def test_mle_mixed_search_with_fp64_finish(exa):
     Z = ctx.simulate(X, Y, th_true, e)
     lb, ub, th0 = [0.01, 0.01, 0.1], [5.0, 2.0, 3.0], [0.5, 0.3, 0.5]
     th64, ll64, st64 = ctx.mle(X, Y, Z, lb, ub, theta0=th0, tol=1e-7, method="lbfgsb", precision="fp64")
-    ctx.set_mixed_policy(0.0)
     thm, llm, stm = ctx.mle(X, Y, Z, lb, ub, theta0=th0, tol=1e-7, method="lbfgsb_fp64_finish",
                             precision="mixed")
     print(f"fp64 {th64} {ll64} {st64}\nmixed+finish {thm} {llm} {stm}")
@@ -250,4 +347,4 @@ def test_mle_mixed_search_with_fp64_finish(exa):
     assert 0 < stm["n_fp64_finish_evals"] < stm["n_grad_evals"]
     # the reported value is an FP64 likelihood at the returned point
     assert ctx.loglik(X, Y, Z, thm) == llm
-    assert abs(llm - ll64) <= 1e-6 * abs(ll64)
+    assert abs(llm - ll64) <= CLAIM * abs(ll64)
