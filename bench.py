@@ -253,13 +253,15 @@ def mle_study(args) -> int:
 
 
 def mle_large(args) -> int:
-    """One estimator on an m x m jittered grid (default 300 x 300, n = 90,000),
-    true theta = (1, beta, 0.5), start (0.5, 0.3, 0.5), tile 768 (one JSON
-    line; progress lines on stderr, one per evaluation).  Estimators:
-    fp64_lbfgsb, fp64_dfo, mixed_dfo, mixed_lbfgsb_fp64_finish; mixed policy
-    --mle-policy: fp32 (FP32 off-diagonal tiles) or bf16_3beta (BF16 beyond
-    3 beta).  theta-hat and l(theta-hat) re-evaluated in FP64 are reported so
-    that runs of different estimators compare directly."""
+    """One estimator on an m x m jittered grid (default 300 x 300, n = 90,000;
+    --big-n-side 400 gives n = 160,000), true theta = (1, --mle-beta,
+    --mle-nu), start (0.5, 0.3, 0.5) or --theta0, tile 768 (one JSON line;
+    progress lines on stderr, one per evaluation).  Estimators: fp64_lbfgsb,
+    fp64_dfo, mixed_lbfgsb, mixed_dfo, mixed_lbfgsb_fp64_finish; mixed map
+    --mle-policy: default (the library's correlation map with one refinement
+    step), fp32 (FP32 off-diagonal tiles) or bf16_3beta (BF16 beyond 3 beta).
+    theta-hat and l(theta-hat) re-evaluated in FP64 are reported so that runs
+    of different estimators compare directly."""
     import torch
 
     import inputgen
@@ -271,10 +273,15 @@ def mle_large(args) -> int:
     e = inputgen.normals(x.size, seed=0)
     X, Y, E = (torch.as_tensor(a, device=dev) for a in (x, y, e))
     ctx = exa.Context(ts=768)
-    th_true = [1.0, beta, 0.5]
+    th_true = [1.0, beta, args.mle_nu]
+    t_sim = time.perf_counter()
     Z = ctx.simulate(X, Y, th_true, E)
     torch.cuda.synchronize()
-    lb, ub, th0 = [0.01, 0.001, 0.1], [5.0, 2.0, 3.0], [0.5, 0.3, 0.5]
+    t_sim = time.perf_counter() - t_sim
+    lb, ub = [0.01, 0.001, 0.1], [5.0, 2.0, 3.0]
+    # a later segment of a long estimation restarts from an earlier one's
+    # best point (the quasi-Newton curvature pairs are not carried over)
+    th0 = list(args.theta0) if args.theta0 else [0.5, 0.3, 0.5]
     meth, prec = {"fp64_lbfgsb": ("lbfgsb", "fp64"), "fp64_dfo": ("dfo", "fp64"), "mixed_dfo": ("dfo", "mixed"),
                   "mixed_lbfgsb": ("lbfgsb", "mixed"),
                   "mixed_lbfgsb_fp64_finish": ("lbfgsb_fp64_finish", "mixed")}[args.mle_estimator]
@@ -293,6 +300,7 @@ def mle_large(args) -> int:
     ctx.set_verbose(False)
     l64 = ctx.loglik_status(X, Y, Z, th_hat, "fp64")[1]
     out = {"study": "mle_large", "n": int(x.size), "grid": f"{m}x{m} jittered, seed 0", "data": "synthetic",
+           "simulate_s": t_sim, "segment_start": "restart" if args.theta0 else "initial",
            "theta_true": th_true, "theta0": th0, "lb": lb, "ub": ub, "estimator": args.mle_estimator,
            "mixed_policy": args.mle_policy if prec == "mixed" else None, "max_evals": args.mle_cap,
            "theta_hat": th_hat, "loglik_reported": l_hat, "loglik_fp64_at_theta_hat": l64, "wall_s": wall,
@@ -440,6 +448,41 @@ def precision_study(args) -> int:
     return 0
 
 
+def profile_mixed(args) -> int:
+    """A short run to profile under rocprofv3: --profile-steps (l, grad l)
+    evaluations in mixed precision (the library's default map) on the m x m
+    jittered grid (--big-n-side, default 200: n = 40,000), theta = (1,
+    --mle-beta, --profile-nu), tile 768, after one warm-up; one JSON line with
+    the per-phase times and tile fractions."""
+    import torch
+
+    import inputgen
+    import paper_1908_06936_amd as exa
+
+    dev = torch.device("cuda:0")
+    m = args.big_n_side
+    x, y = inputgen.jittered_grid(m, seed=0)
+    X, Y = torch.as_tensor(x, device=dev), torch.as_tensor(y, device=dev)
+    E = torch.as_tensor(inputgen.normals(x.size, seed=0), device=dev)
+    th = [1.0, args.mle_beta, args.profile_nu]
+    ctx = exa.Context(ts=768)
+    Z = ctx.simulate(X, Y, th, E)
+    prec = args.profile_precision
+    ctx.loglik_grad(X, Y, Z, th, prec)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.profile_steps):
+        ll, g = ctx.loglik_grad(X, Y, Z, th, prec)
+        print(f"[profile] step {s + 1}/{args.profile_steps} l={ll:.10g}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.profile_steps
+    tm = ctx.timings()
+    print(json.dumps({"study": "profile", "n": int(x.size), "theta": th, "precision": prec, "s_per_step": dt,
+                      "timings": tm}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -465,6 +508,9 @@ def main() -> int:
     ap.add_argument("--mle-large", action="store_true",
                     help="instead of the throughput step: one estimator on the --big-n-side grid (see mle_large)")
     ap.add_argument("--mle-beta", type=float, default=0.03)
+    ap.add_argument("--mle-nu", type=float, default=0.5, help="true nu of --mle-large")
+    ap.add_argument("--theta0", type=float, nargs=3, default=None,
+                    help="start of --mle-large (default (0.5, 0.3, 0.5)); a restart point for a second segment")
     ap.add_argument("--mle-estimator", default="fp64_lbfgsb",
                     choices=["fp64_lbfgsb", "fp64_dfo", "mixed_dfo", "mixed_lbfgsb", "mixed_lbfgsb_fp64_finish"])
     ap.add_argument("--mle-policy", default="default", choices=["default", "fp32", "bf16_3beta"])
@@ -474,6 +520,11 @@ def main() -> int:
                          "precision maps (see precision_study)")
     ap.add_argument("--precision-policies", nargs="+", choices=sorted(PRECISION_POLICIES), default=None)
     ap.add_argument("--precision-skip-90k", action="store_true")
+    ap.add_argument("--profile-mixed", action="store_true",
+                    help="instead of the throughput step: a short (l, grad l) run to profile (see profile_mixed)")
+    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--profile-nu", type=float, default=0.5)
+    ap.add_argument("--profile-precision", default="mixed", choices=["mixed", "fp64"])
     args = ap.parse_args()
 
     if args.copy_calibration:
@@ -487,6 +538,12 @@ def main() -> int:
         print(json.dumps({"copy_bytes": src.numel() * 8}))
         return 0
 
+    if args.profile_mixed:
+        if args.big_n_side == 400 and "--big-n-side" not in sys.argv:
+            args.big_n_side = 200
+        if "--mle-beta" not in sys.argv:
+            args.mle_beta = 0.1
+        return profile_mixed(args)
     if args.mle_study:
         return mle_study(args)
     if args.precision_study:
@@ -586,6 +643,44 @@ def main() -> int:
         "loglik": lls[-1][0],
         "grad": lls[-1][1],
     }
+    # the two small studies of the workload list: n = 10,000 (100 x 100
+    # jittered grid, tile 512, six (beta, nu)), one l each; n = 400 (20 x 20
+    # jittered grid, theta = (1, 0.1, 0.5)), one l and the derivative-free MLE
+    # from the lower bound (0.001, 0.001, 0.001) with tolerance 1e-4
+    ctx.set_profiling(False)
+    x2, y2 = inputgen.jittered_grid(100, seed=0)
+    X2, Y2 = torch.as_tensor(x2, device=dev), torch.as_tensor(y2, device=dev)
+    E2 = torch.as_tensor(inputgen.normals(x2.size, seed=0), device=dev)
+    ctx2 = exa.Context(ts=512, device=0)
+    c2 = {}
+    for nu in (0.5, 1.0):
+        for beta in (0.03, 0.1, 0.3):
+            th2 = [1.0, beta, nu]
+            Z2 = ctx2.simulate(X2, Y2, th2, E2)
+            ctx2.loglik(X2, Y2, Z2, th2)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            l2 = ctx2.loglik(X2, Y2, Z2, th2)
+            torch.cuda.synchronize()
+            c2[f"beta={beta},nu={nu}"] = {"loglik": l2, "ms": 1e3 * (time.perf_counter() - t1)}
+    result["n10000_grid_ts512_one_loglik"] = c2
+    x1, y1 = inputgen.jittered_grid(20, seed=0)
+    X1, Y1 = torch.as_tensor(x1, device=dev), torch.as_tensor(y1, device=dev)
+    E1 = torch.as_tensor(inputgen.normals(x1.size, seed=0), device=dev)
+    th1 = [1.0, 0.1, 0.5]
+    Z1 = ctx2.simulate(X1, Y1, th1, E1)
+    ctx2.loglik(X1, Y1, Z1, th1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    l1 = ctx2.loglik(X1, Y1, Z1, th1)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    th1_hat, l1_hat, st1 = ctx2.mle(X1, Y1, Z1, [0.001] * 3, [5.0] * 3, tol=1e-4, method="dfo")
+    result["n400_grid"] = {"loglik": l1, "loglik_ms": 1e3 * (t2 - t1), "dfo_theta_hat": th1_hat,
+                           "dfo_loglik": l1_hat, "dfo_wall_s": st1["total_s"], "dfo_evals": st1["n_evals"],
+                           "dfo_per_eval_ms": 1e3 * st1["per_eval_s"], "dfo_status": st1["status"]}
+    ctx2.close()
+    print("[bench] n = 10,000 and n = 400 studies done", file=sys.stderr, flush=True)
     # kriging at 1,000 new points from the same data (factorisation included)
     xq, yq = inputgen.uniform(1000, seed=5)
     Xq, Yq = torch.as_tensor(xq, device=dev), torch.as_tensor(yq, device=dev)

@@ -70,8 +70,9 @@ typedef int32_t exageo_status;
 #define EXAGEO_LBFGSB 1 /* bounded quasi-Newton on (l, grad l)                */
 /* with EXAGEO_MIXED: the quasi-Newton search on the mixed-precision (l, grad l)
  * until its accepted l improve by less than 1e-6 |l| (the level of the mixed
- * error), then the same search in FP64 from there (ending after three
- * accepted steps in a row below tol); other precisions: as EXAGEO_LBFGSB */
+ * error), then the same search in FP64 from there, continuing with the
+ * quasi-Newton model (curvature pairs) the mixed search built and ending after
+ * two accepted steps in a row below tol; other precisions: as EXAGEO_LBFGSB */
 #define EXAGEO_LBFGSB_FP64_FINISH 2
 
 typedef struct exageo_ctx exageo_ctx;
@@ -102,8 +103,13 @@ void exageo_destroy(exageo_ctx *ctx);
 exageo_status exageo_set_stream(exageo_ctx *ctx, void *hip_stream);
 
 /* Device bytes the library needs for a problem of size n (tile storage,
- * sorted copies, solve vectors, schedules).  want_grad adds the buffers of the
- * gradient. */
+ * sorted copies, solve vectors, schedules).  want_grad: 0 = l alone, 1 = with
+ * the gradient (also what exageo_predict with mse needs: its blocks of new
+ * points use the gradient's staging buffer), 2 = exageo_fisher (adds one
+ * buffer of lower tiles, npad^2 / 2 doubles, for each of dSigma_beta and
+ * dSigma_nu and a strip of about npad^2 / 8 doubles; npad = n rounded up to a
+ * multiple of ts), 3 = exageo_fisher with a nugget (a third buffer, for
+ * dSigma_sigma2).  0 for invalid arguments. */
 size_t exageo_workspace_bytes(int64_t n, int64_t ts, int precision, int want_grad);
 
 /* Hand the library a caller-owned device buffer (e.g. a torch tensor) to use
@@ -237,8 +243,9 @@ exageo_status exageo_loglik_grad_noalloc(exageo_ctx *ctx, int64_t n, const doubl
  * c_i the covariances between new point i and the observed points.  x, y, z
  * (n) and xnew, ynew, mean, mse (m) are DEVICE pointers in the caller's order;
  * mse may be NULL (mean only: one fused pass over the n m pairs); with mse the
- * library solves L V = C for blocks of up to 512 new points on MFMA, using a
- * buffer of 2 * npad * 512 doubles it allocates itself (ENOMEM if it cannot).
+ * library solves L V = C for blocks of up to 512 new points on MFMA in the
+ * workspace's gradient staging buffer (the workspace must then hold the
+ * want_grad = 1 plan, else ENOMEM).
  * Statuses as for exageo_loglik (ENOTPD with *info when Sigma is not positive
  * definite). */
 exageo_status exageo_predict(exageo_ctx *ctx, int64_t n, const double *x, const double *y, const double *z,
@@ -252,12 +259,15 @@ exageo_status exageo_predict(exageo_ctx *ctx, int64_t n, const double *x, const 
  * computed in FP64 whatever the context's precision settings, as
  * I_jk = <B_j, B_k> / 2 with B_j = L^-1 dSigma_j L^-T (B_sigma2 = I / sigma2
  * without a nugget; B_beta, B_nu and, with a nugget, B_sigma2 by FP64 MFMA
- * products with the regenerated derivative matrices).  x, y are DEVICE pointers (n doubles, caller order); fisher is a
- * HOST array of 9 doubles receiving I row-major.  The library allocates
- * 3 npad^2 doubles of its own for the call (npad = n rounded up to the tile
- * size; 4 npad^2 with a nugget, which needs B_sigma2 too) and frees them
- * before returning (ENOMEM if it cannot).  EINVAL while
- * the DST approximation is on; ENOTPD with *info as for exageo_loglik. */
+ * products with the derivative matrices regenerated strip by strip).  x, y are
+ * DEVICE pointers (n doubles, caller order); fisher is a HOST array of 9
+ * doubles receiving I row-major.  Every buffer comes from the workspace
+ * (exageo_workspace_bytes with want_grad = 2, or 3 with a nugget, which needs
+ * B_sigma2 too): each B_j is one set of lower tiles, npad^2 / 2 doubles, so
+ * with 288 GB of device memory n reaches about 140,000 (125,000 with a
+ * nugget).  ENOMEM if the
+ * workspace is smaller; EINVAL while the DST approximation is on; ENOTPD with
+ * *info as for exageo_loglik. */
 exageo_status exageo_fisher(exageo_ctx *ctx, int64_t n, const double *x, const double *y, const double theta[3],
                             double fisher[9], int64_t *info);
 

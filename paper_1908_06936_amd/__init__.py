@@ -90,6 +90,7 @@ class Context:
         self._h = h
         self._ws = None
         self._ws_key = None
+        self._nugget = 0.0
         # mixed precision: the library's correlation map unless distance bands are asked for
         if band_factor is not None or fp64_band is not None:
             self.set_mixed_policy(3.0 if band_factor is None else band_factor,
@@ -103,7 +104,8 @@ class Context:
     def _sync_stream(self):
         self._lib.exageo_set_stream(self._h, self._stream_handle())
 
-    def _ensure_ws(self, n: int, precision: int, want_grad: bool):
+    def _ensure_ws(self, n: int, precision: int, want_grad):
+        # want_grad: False / True, or 2 / 3 for the Fisher information (see exageo_workspace_bytes)
         need = self._lib.exageo_workspace_bytes(n, self.ts, precision, int(want_grad))
         if need == 0:
             raise ExaGeoError(EINVAL, f"bad problem size n={n}, ts={self.ts}")
@@ -168,6 +170,7 @@ class Context:
         """Fixed nugget: tau2 added to the diagonal of Sigma in every later
         call (0 = none)."""
         self._check(self._lib.exageo_set_nugget(self._h, float(tau2)), "set_nugget")
+        self._nugget = float(tau2)
 
     def set_dst_band(self, band: int):
         """DST approximation of the likelihood calls: tiles |I - J| >= band
@@ -296,7 +299,7 @@ class Context:
         mean = torch.empty(m, dtype=torch.float64, device=x.device)
         mse = torch.empty(m, dtype=torch.float64, device=x.device) if with_mse else None
         self._sync_stream()
-        self._ensure_ws(n, FP64, False)
+        self._ensure_ws(n, FP64, True)  # the variance blocks use the gradient plan's staging buffer
         info = ctypes.c_int64(0)
         st = self._lib.exageo_predict(self._h, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                       ctypes.c_void_p(z.data_ptr()), _lib.darr(theta), m,
@@ -314,7 +317,7 @@ class Context:
         n = x.numel()
         y = _dev_f64(y, "y", n)
         self._sync_stream()
-        self._ensure_ws(n, FP64, True)
+        self._ensure_ws(n, FP64, 3 if self._nugget > 0 else 2)  # derivative matrices in the workspace
         out = (ctypes.c_double * 9)()
         info = ctypes.c_int64(0)
         st = self._lib.exageo_fisher(self._h, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),

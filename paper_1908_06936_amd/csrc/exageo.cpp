@@ -30,7 +30,9 @@ struct Plan {
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
          off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_p32 = 0, off_pbt = 0, off_tag = 0,
          off_tbox = 0, off_pool = 0, off_pidx = 0, off_bli = 0, off_blj = 0, off_corr = 0, off_rtry = 0,
-         off_rnrm = 0;
+         off_rnrm = 0, off_fb = 0, off_fstrip = 0, off_fpart = 0, off_fout = 0;
+  size_t ptmp_doubles = 0;  // FP64 staging of the inverse (also the kriging blocks)
+  int nfisher = 0;          // derivative matrices held for the Fisher information (0, 2 or 3)
   int64_t pool_cap = 0;  // mixed precision: FP64 band tiles the pool can hold
   int64_t dst = 0;       // DST tile band (0: exact)
   size_t bytes = 0;
@@ -38,6 +40,8 @@ struct Plan {
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// want_grad: 0 = l, 1 = l and its gradient, 2 = also the Fisher information
+// (two derivative matrices), 3 = the Fisher information with a nugget (three)
 Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64) {
   Plan p;
   p.n = n;
@@ -80,8 +84,12 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
   }
   p.off_xd = take((size_t)p.NT * tt * 8);
   // FP64 inverse: FP64 staging buffer (the mixed inverse stages in the FP32 panel copy)
-  // (two halves: consecutive TRTRI steps stage on different streams)
-  p.off_ptmp = p.grad && !p.mixed ? take(2 * (size_t)std::max<int64_t>(1, p.NT - 1) * tt * 8) : 0;
+  // (two halves: consecutive TRTRI steps stage on different streams); kriging
+  // uses it for its blocks of at least 128 new points (2 npad 128 doubles)
+  if (p.grad && !p.mixed) {
+    p.ptmp_doubles = std::max(2 * (size_t)std::max<int64_t>(1, p.NT - 1) * tt, 2 * (size_t)p.npad * BLKH);
+    p.off_ptmp = take(p.ptmp_doubles * 8);
+  }
   p.off_dinv = take((size_t)p.NT * p.T * BLKH * BLKH * 8);
   p.off_ld = take((size_t)p.NT * p.T * 8);
   p.off_xs = take((size_t)p.npad * 8);
@@ -100,6 +108,16 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
   p.off_part = take((size_t)(p.grad ? exg::lauum_blocks(ts, p.NT) + p.pool_cap * p.T * p.T : 1) * 3 * 8);
   p.off_out = take(16 * 8);
   p.off_info = take(8);
+  if (want_grad >= 2 && !p.mixed) {
+    // Fisher information: one buffer of lower tiles per derivative matrix, a
+    // strip of tile rows shared by the regenerated derivatives and the staging
+    p.nfisher = want_grad == 3 ? 3 : 2;
+    const size_t low = (size_t)p.NT * (p.NT + 1) / 2 * tt;
+    p.off_fb = take((size_t)p.nfisher * low * 8);
+    p.off_fstrip = take(exg::fisher_strip_doubles(ts, p.NT) * 8);
+    p.off_fpart = take((size_t)exg::fisher_part_blocks(ts, p.NT) * 9 * 8);
+    p.off_fout = take(16 * 8);
+  }
   p.bytes = o;
   return p;
 }
@@ -151,9 +169,6 @@ struct exageo_ctx {
   int32_t* hband = nullptr;  // pinned: pidx (noff) then li, lj (pool_cap each)
   size_t hband_words = 0;
   std::vector<int64_t> bfirst;
-  // kriging variance: library-owned right-hand-side blocks (C and V = L^-1 C)
-  double* pred_buf = nullptr;
-  size_t pred_bytes = 0;
   // side stream (default priority) for the lookahead panel, and its events
   hipStream_t side = nullptr;
   hipEvent_t ev_col = nullptr, ev_panel = nullptr;
@@ -714,7 +729,6 @@ void exageo_destroy(exageo_ctx* c) {
   if (c->htag) (void)hipHostFree(c->htag);
   if (c->hcorr) (void)hipHostFree(c->hcorr);
   if (c->hband) (void)hipHostFree(c->hband);
-  if (c->pred_buf) (void)hipFree(c->pred_buf);
   for (int i = 0; i < c->nev_created; ++i) (void)hipEventDestroy(c->ev[i]);
   if (c->side) {
     (void)hipStreamSynchronize(c->side);
@@ -732,7 +746,8 @@ exageo_status exageo_set_stream(exageo_ctx* c, void* hip_stream) {
 }
 
 size_t exageo_workspace_bytes(int64_t n, int64_t ts, int precision, int want_grad) {
-  if (n < 1 || ts < BLKH || ts % BLKH != 0) return 0;
+  if (n < 1 || ts < BLKH || ts % BLKH != 0 || want_grad < 0 || want_grad > 3) return 0;
+  if (precision != EXAGEO_FP64 && precision != EXAGEO_MIXED) return 0;
   return make_plan(n, ts, want_grad, precision).bytes;
 }
 
@@ -1053,14 +1068,17 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
   } else if (!finish64) {
     res = exg::maximize_lbfgsb(obj, lb, ub, th0, tol, max_iters);
   } else {
-    // the mixed score carries an error of the order of the mixed l's (its
-    // factor is a perturbed Sigma's), which stalls the search near the optimum:
-    // search in mixed precision while l still improves by more than 1e-6 |l|
-    // (at most half the budget, 40 evaluations when unlimited), then finish
-    // in FP64 from the best mixed point.  The finish starts without curvature
-    // pairs, so one small first step does not end it: three in a row do
+    // the mixed l carries rounding noise of the order of its error (its
+    // factor is a perturbed Sigma's), which keeps the search from meeting an
+    // absolute tol at large n: search in mixed precision while l still
+    // improves by more than 1e-6 |l| (at most half the budget, 40 evaluations
+    // when unlimited), then finish in FP64 from the best mixed point with the
+    // quasi-Newton model the mixed search built (its scores are accurate), so
+    // that the finish takes model steps at once; it ends after two accepted
+    // steps in a row below tol
     const int cap1 = max_iters > 0 ? std::max(1, max_iters / 2) : 40;
-    const exg::MleResult r1 = exg::maximize_lbfgsb(obj, lb, ub, th0, tol, cap1, 1e-6);
+    exg::Curvature curv;
+    const exg::MleResult r1 = exg::maximize_lbfgsb(obj, lb, ub, th0, tol, cap1, 1e-6, 1, &curv);
     if (first_err != EXAGEO_OK) return first_err;
     double th1[3];
     for (int k = 0; k < 3; ++k) th1[k] = std::isfinite(r1.f) ? r1.theta[k] : th0[k];
@@ -1070,7 +1088,7 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
     if (st) return st;
     const int64_t used = nev + ngev, before = ngev;
     const int cap2 = max_iters > 0 ? (int)std::max<int64_t>(1, max_iters - used) : 0;
-    res = exg::maximize_lbfgsb(obj, lb, ub, th1, tol, cap2, 0.0, 3);
+    res = exg::maximize_lbfgsb(obj, lb, ub, th1, tol, cap2, 0.0, curv.count > 0 ? 2 : 3, &curv);
     res.iters += r1.iters;
     nfinish = ngev - before;
   }
@@ -1091,8 +1109,6 @@ exageo_status exageo_mle(exageo_ctx* c, int64_t n, const double* x, const double
   return res.converged ? EXAGEO_OK : fail(c, EXAGEO_ENOCONV, "max_iters reached before tol");
 }
 
-}  // extern "C"
-
 exageo_status exageo_predict(exageo_ctx* c, int64_t n, const double* x, const double* y, const double* z,
                              const double theta[3], int64_t m, const double* xnew, const double* ynew, double* mean,
                              double* mse, int64_t* info) {
@@ -1103,7 +1119,7 @@ exageo_status exageo_predict(exageo_ctx* c, int64_t n, const double* x, const do
     return fail(c, EXAGEO_EINVAL, "predict: invalid argument");
   if (n > (int64_t)INT32_MAX || m > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n or m too large");
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
-  Plan p = make_plan(n, c->ts, 0, EXAGEO_FP64);
+  Plan p = make_plan(n, c->ts, 1, EXAGEO_FP64);  // the gradient plan: its staging holds the kriging blocks
   exageo_status st = ensure_ws(c, p);
   if (st) return st;
   c->plan = p;
@@ -1125,25 +1141,12 @@ exageo_status exageo_predict(exageo_ctx* c, int64_t n, const double* x, const do
   exg::launch_krige_mean(at<double>(c, p.off_xs), at<double>(c, p.off_ys), av, p.n, xnew, ynew, m,
                          at<double>(c, p.off_qt), at<double>(c, p.off_cst), mean, c->stream);
   if (mse) {
-    // blocks of up to 512 new points: C = Sigma(obs, new), V = L^-1 C
-    const int64_t mcap = std::min<int64_t>(512, (m + 127) / 128 * 128);
-    const size_t need = 2 * (size_t)p.npad * (size_t)mcap * 8;
-    if (c->pred_bytes < need) {
-      if (c->pred_buf) {
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        HIPCHK(c, hipFree(c->pred_buf));
-        c->pred_buf = nullptr;
-        c->pred_bytes = 0;
-      }
-      hipError_t e = hipMalloc((void**)&c->pred_buf, need);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(c, EXAGEO_ENOMEM, "predict: hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
-      }
-      c->pred_bytes = need;
-    }
-    double* Cb = c->pred_buf;
-    double* Vb = c->pred_buf + (size_t)p.npad * mcap;
+    // blocks of up to 512 new points (as many as the staging buffer holds, at
+    // least 128): C = Sigma(obs, new), V = L^-1 C
+    const int64_t fit = (int64_t)(p.ptmp_doubles / (2 * (size_t)p.npad)) / 128 * 128;
+    const int64_t mcap = std::min<int64_t>(std::min<int64_t>(512, fit), (m + 127) / 128 * 128);
+    double* Cb = at<double>(c, p.off_ptmp);
+    double* Vb = Cb + (size_t)p.npad * mcap;
     for (int64_t c0 = 0; c0 < m; c0 += mcap) {
       const int64_t cols = std::min<int64_t>(mcap, (m - c0 + 127) / 128 * 128);
       exg::launch_krige_mse(M, Xd, at<double>(c, p.off_xs), at<double>(c, p.off_ys), p.n, xnew, ynew, m, c0, cols,
@@ -1164,7 +1167,8 @@ exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const dou
   if (n > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n too large");
   if (c->dst_band > 0) return fail(c, EXAGEO_EINVAL, "the Fisher information is computed for the exact covariance only");
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
-  Plan p = make_plan(n, c->ts, 1, EXAGEO_FP64);
+  const bool nug = c->nugget > 0.0;  // B_sigma2 is then not I / sigma2
+  Plan p = make_plan(n, c->ts, nug ? 3 : 2, EXAGEO_FP64);
   exageo_status st = ensure_ws(c, p);
   if (st) return st;
   c->plan = p;
@@ -1177,16 +1181,6 @@ exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const dou
   double ll = 0.0;
   st = eval_sorted(c, p, theta, false, &ll, nullptr, info, true);
   if (st) return st;
-  const int64_t nparts = exg::fisher_part_blocks(p.ts, p.NT);
-  const size_t full = (size_t)p.npad * (size_t)p.npad;
-  const bool nug = c->nugget > 0.0;  // B_sigma2 is then not I / sigma2
-  const size_t need = ((nug ? 4 : 3) * full + 9 * (size_t)nparts + 16) * 8;
-  double* buf = nullptr;
-  hipError_t e = hipMalloc((void**)&buf, need);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(c, EXAGEO_ENOMEM, "fisher: hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
-  }
   const exg::TileMat M = tilemat(c, p);
   double* Xd = at<double>(c, p.off_xd);
   // L^-1 in place (the tile matrix then holds X = L^-1, lower-triangular tiles)
@@ -1197,40 +1191,38 @@ exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const dou
         c, p.NT,
         [&](int64_t k, hipStream_t s) { exg::launch_trtri_right(M, Xd + k * tt, P64 + (k & 1) * half, k, p.n, s); },
         [&](int64_t k, hipStream_t s) { exg::launch_trtri_rest(M, Xd + k * tt, P64 + (k & 1) * half, k, p.n, s); });
-    if (st) {
-      (void)hipFree(buf);
-      return st;
-    }
+    if (st) return st;
   }
-  double* Bb = buf;                // dSigma_beta, then B_beta
-  double* Mb = buf + full;         // X dSigma_j
-  double* Bn = buf + 2 * full;     // dSigma_nu, then B_nu
-  double* Bs = nug ? buf + 3 * full : nullptr;  // dSigma_sigma2, then B_sigma2
-  double* part = buf + (nug ? 4 : 3) * full;     // partial sums of the traces and products
-  double* out = part + 9 * nparts;
+  const size_t low = (size_t)p.NT * (p.NT + 1) / 2 * (size_t)p.ts * p.ts;
+  double* fb = at<double>(c, p.off_fb);
+  double* Bb = fb;                       // B_beta
+  double* Bn = fb + low;                 // B_nu
+  double* Bs = nug ? fb + 2 * low : nullptr;  // B_sigma2
+  double* strip = at<double>(c, p.off_fstrip);
+  double* out = at<double>(c, p.off_fout);
   const double* xs = at<double>(c, p.off_xs);
   const double* ys = at<double>(c, p.off_ys);
   const double* qt = at<double>(c, p.off_qt);
   const double* cst = at<double>(c, p.off_cst);
-  exg::launch_fisher_param(M, 1, p.n, xs, ys, qt, cst, Bb, Mb, Bb, c->stream);
-  exg::launch_fisher_param(M, 2, p.n, xs, ys, qt, cst, Bn, Mb, Bn, c->stream);
-  if (nug) exg::launch_fisher_param(M, 0, p.n, xs, ys, qt, cst, Bs, Mb, Bs, c->stream);
-  exg::launch_fisher_reduce(Bs, Bb, Bn, p.ts, p.NT, p.n, cst, part, out, c->stream);
+  exg::launch_fisher_param(M, 1, p.n, xs, ys, qt, cst, strip, Bb, c->stream);
+  exg::launch_fisher_param(M, 2, p.n, xs, ys, qt, cst, strip, Bn, c->stream);
+  if (nug) exg::launch_fisher_param(M, 0, p.n, xs, ys, qt, cst, strip, Bs, c->stream);
+  exg::launch_fisher_reduce(Bs, Bb, Bn, p.ts, p.NT, p.n, cst, at<double>(c, p.off_fpart), out, c->stream);
   rec(c, 5);
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(fisher, out, 9 * 8, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e == hipSuccess && c->profiling) {
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(c->hres, out, 9 * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  memcpy(fisher, c->hres, 9 * 8);
+  if (c->profiling) {
     c->timings[0] = ev_ms(c, 0, 5);
     c->timings[7] = ev_ms(c, 4, 5);
     // MFMA flops of the two products per parameter over the R real 128-blocks:
-    // X G (row block g runs over (g + 1) 128 columns of X) and M X^T (lower
-    // block pairs (g, h), h <= g, over (h + 1) 128 columns)
+    // X G and M X^T over the lower block pairs (g, h), h <= g, each with a
+    // range of (g + 1) or (h + 1) 128-columns
     const double R = (double)((p.n + BLKH - 1) / BLKH), b3 = 2.0 * BLKH * BLKH * BLKH;
-    c->timings[18] = (nug ? 3.0 : 2.0) * b3 * (R * R * (R + 1.0) / 2.0 + R * (R + 1.0) * (R + 2.0) / 6.0);
+    c->timings[18] = (nug ? 3.0 : 2.0) * b3 * 2.0 * (R * (R + 1.0) * (R + 2.0) / 6.0);
   }
-  const hipError_t ef = hipFree(buf);
-  if (e != hipSuccess) return fail(c, EXAGEO_EDEVICE, "fisher: %s", hipGetErrorString(e));
-  if (ef != hipSuccess) return fail(c, EXAGEO_EDEVICE, "fisher: hipFree: %s", hipGetErrorString(ef));
   return EXAGEO_OK;
 }
+
+}  // extern "C"

@@ -105,10 +105,13 @@ void launch_krige_mse(const TileMat& M, const double* Xd, const double* xs, cons
                       const double* xn, const double* yn, int64_t m, int64_t c0, int64_t ncols, const double* qt,
                       const double* cst, double* C, double* V, double* mse, hipStream_t s);
 
-// k_fisher.hip (X: the tile matrix holding L^-1; G, Mb, Bs, Bb, Bn: NT^2 full tiles each)
+// k_fisher.hip (X: the tile matrix holding L^-1; B's: lower tiles packed by
+// tile columns, n^2 / 2 doubles each)
 int64_t fisher_part_blocks(int64_t ts, int64_t NT);
+// doubles of the strip shared by the regenerated derivative rows and the staging
+size_t fisher_strip_doubles(int64_t ts, int64_t NT);
 void launch_fisher_param(const TileMat& X, int comp, int64_t nreal, const double* xs, const double* ys,
-                         const double* qt, const double* cst, double* G, double* Mb, double* Bs, hipStream_t s);
+                         const double* qt, const double* cst, double* S, double* Bm, hipStream_t s);
 // Bs: B_sigma2 or null (B_sigma2 = I / sigma2); part: 9 fisher_part_blocks
 // doubles; out: 9 doubles (device)
 void launch_fisher_reduce(const double* Bs, const double* Bb, const double* Bn, int64_t ts, int64_t NT, int64_t nreal,

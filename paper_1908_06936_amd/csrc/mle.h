@@ -25,6 +25,18 @@ struct MleResult {
 MleResult maximize_dfo(const Objective& f, const double lb[3], const double ub[3], const double theta0[3], double tol,
                        int max_evals);
 
+// The curvature pairs (s, y) of the quasi-Newton model, in u = log theta.
+// maximize_lbfgsb starts from the pairs in `curv` when it is given and holds
+// any, and leaves its own pairs there on return, so that a second search
+// (e.g. an FP64 finish after a mixed-precision search) continues with the
+// model the first one built instead of a steepest-descent restart.
+struct Curvature {
+  static constexpr int M = 6;
+  double s[M][3], y[M][3], rho[M];
+  int count = 0, head = 0;
+};
+
+
 // Projected limited-memory BFGS on u = log theta within [log lb, log ub]:
 // variables at a bound whose gradient points outward are held fixed, the
 // two-loop recursion (Nocedal, Math. Comp. 35, 1980) gives the step on the free
@@ -34,6 +46,6 @@ MleResult maximize_dfo(const Objective& f, const double lb[3], const double ub[3
 // successive accepted l differ by less than tol + rtol |l| (patience times in a
 // row), or after max_evals.
 MleResult maximize_lbfgsb(const Objective& f, const double lb[3], const double ub[3], const double theta0[3],
-                          double tol, int max_evals, double rtol = 0.0, int patience = 1);
+                          double tol, int max_evals, double rtol = 0.0, int patience = 1, Curvature* curv = nullptr);
 
 }  // namespace exg

@@ -166,7 +166,7 @@ MleResult maximize_dfo(const Objective& obj, const double lb[3], const double ub
 
 // ------------------------------------------------------- projected L-BFGS
 MleResult maximize_lbfgsb(const Objective& obj, const double lb[3], const double ub[3], const double theta0[3],
-                          double tol, int max_evals, double rtol, int patience) {
+                          double tol, int max_evals, double rtol, int patience, Curvature* curv) {
   const Box box = log_box(lb, ub);
   MleResult res{};
   res.f = -std::numeric_limits<double>::infinity();
@@ -187,9 +187,20 @@ MleResult maximize_lbfgsb(const Objective& obj, const double lb[3], const double
     return -f;
   };
   auto budget_left = [&]() { return max_evals <= 0 || nev < max_evals; };
-  constexpr int M = 6;
+  constexpr int M = Curvature::M;
   double sm[M][D], ym[M][D], rhom[M];
   int mcount = 0, mhead = 0;
+  if (curv && curv->count > 0) {
+    for (int i = 0; i < M; ++i) {
+      for (int k = 0; k < D; ++k) {
+        sm[i][k] = curv->s[i][k];
+        ym[i][k] = curv->y[i][k];
+      }
+      rhom[i] = curv->rho[i];
+    }
+    mcount = std::min(curv->count, M);
+    mhead = curv->head % M;
+  }
 
   double u[D], g[D];
   for (int k = 0; k < D; ++k) u[k] = std::log(theta0[k]);
@@ -320,6 +331,17 @@ MleResult maximize_lbfgsb(const Objective& obj, const double lb[3], const double
       conv = true;
       break;
     }
+  }
+  if (curv) {
+    for (int i = 0; i < M; ++i) {
+      for (int k = 0; k < D; ++k) {
+        curv->s[i][k] = sm[i][k];
+        curv->y[i][k] = ym[i][k];
+      }
+      curv->rho[i] = rhom[i];
+    }
+    curv->count = mcount;
+    curv->head = mhead;
   }
   res.iters = it;
   res.evals = nev;

@@ -61,6 +61,28 @@ def test_workspace_bytes_host_only(lib):
     assert 0.9 * a < m < 1.25 * a
 
 
+def test_workspace_of_the_fisher_information(lib):
+    # the derivative matrices take one buffer of lower tiles each (npad^2 / 2
+    # doubles), two without a nugget and three with one, plus a strip of about
+    # npad^2 / 8 doubles; kriging borrows the gradient plan's staging buffer
+    from paper_1908_06936_amd._lib import FP64, MIXED
+
+    ws = lib.exageo_workspace_bytes
+    for n, ts in ((40000, 768), (90000, 768), (10000, 512)):
+        nt = (n + ts - 1) // ts
+        low = nt * (nt + 1) // 2 * ts * ts * 8
+        npad2 = (nt * ts) ** 2 * 8
+        g = ws(n, ts, FP64, 1)
+        f2, f3 = ws(n, ts, FP64, 2), ws(n, ts, FP64, 3)
+        w = nt if nt < 8 else (nt + 7) // 8  # strip: w tile rows of the derivative matrix
+        strip = w * nt * ts * ts * 8
+        parts = -(-(nt * (nt + 1) // 2 * (ts // 128) ** 2 * 9 * 8) // 256) * 256
+        assert f2 - g == 2 * low + strip + parts + 256
+        assert strip <= npad2 / 6
+        assert f3 - f2 == low
+    assert ws(1000, 256, FP64, 4) == 0 and ws(1000, 256, 7, 1) == 0
+
+
 def test_entry_points_reject_bad_arguments_before_any_launch(lib):
     from paper_1908_06936_amd._lib import EINVAL
 

@@ -97,6 +97,25 @@ def test_fisher_markov_full_size(exa):
     assert np.all(np.linalg.eigvalsh(I) > 0)
 
 
+def test_fisher_config4_size(exa):
+    # n = 90,000 (300 x 300 jittered grid), tile 768: the derivative matrices
+    # live in the workspace as lower tiles (n^2 / 2 doubles each); checks that
+    # hold at any size: I_ss = n / (2 sigma^4), I_sk = -g_k / sigma^2 against
+    # the score at z = 0, symmetry and positive definiteness
+    x, y = inputgen.jittered_grid(300, seed=0)
+    n, th = x.size, [1.0, 0.1, 0.5]
+    ctx = exa.Context(ts=768)
+    ctx.set_profiling(True)
+    I = ctx.fisher(dev(x), dev(y), th)
+    tm = ctx.timings()
+    print(f"n={n}: I = {I.tolist()}, {tm['total_ms']:.0f} ms, products {tm['fisher_flops'] / (tm['grad_ms'] * 1e-3) / 1e12:.1f} TFLOP/s")
+    _, g = ctx.loglik_grad(dev(x), dev(y), dev(np.zeros(n)), th)
+    assert I[0, 0] == n / (2 * th[0] ** 2)
+    np.testing.assert_allclose(I[0, 1:], -np.asarray(g[1:]) / th[0], rtol=1e-9)
+    np.testing.assert_array_equal(I, I.T)
+    assert np.all(np.linalg.eigvalsh(I) > 0)
+
+
 def test_fisher_variance_row_is_the_score_trace_at_full_size(exa):
     # at any size: I_ss = n / (2 sigma^4), and with z = 0 the score is
     # g_k = -tr(Sigma^-1 dSigma_k) / 2, so I_sk = -g_k / sigma^2 (the score runs
