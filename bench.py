@@ -647,7 +647,6 @@ def main() -> int:
     # jittered grid, tile 512, six (beta, nu)), one l each; n = 400 (20 x 20
     # jittered grid, theta = (1, 0.1, 0.5)), one l and the derivative-free MLE
     # from the lower bound (0.001, 0.001, 0.001) with tolerance 1e-4
-    ctx.set_profiling(False)
     x2, y2 = inputgen.jittered_grid(100, seed=0)
     X2, Y2 = torch.as_tensor(x2, device=dev), torch.as_tensor(y2, device=dev)
     E2 = torch.as_tensor(inputgen.normals(x2.size, seed=0), device=dev)

@@ -34,7 +34,9 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) { return f32_to_bf16_rn
 // C(m, n) += alpha acc over one 128 x 128 block of the off-diagonal tile
 // whose slot starts at `tile` (in-tile element offset o0 of the block's first
 // entry, leading dimension ld): FP32 tiles in place, BF16 tiles (first half of
-// the slot) widened, updated and rounded to nearest even.
+// the slot) widened, updated and rounded to nearest even.  The 16 values of
+// one accumulator are loaded before any is stored, so that the loads are not
+// waited for one by one.
 __device__ __forceinline__ void acc32_update(void* tile, bool bf, int64_t o0, int64_t ld, const v16f (&acc)[2][2],
                                              float alpha) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
@@ -42,19 +44,25 @@ __device__ __forceinline__ void acc32_update(void* tile, bool bf, int64_t o0, in
   for (int x = 0; x < 2; ++x) {
     const int m = wr * 64 + 32 * x + (lane & 31);
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < 2; ++y) {
+      const int64_t ob = o0 + m + (int64_t)(wc * 64 + 32 * y + 4 * (lane >> 5)) * ld;
+      if (!bf) {
+        float* C = (float*)tile + ob;
+        float old[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int n = wc * 64 + 32 * y + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t o = o0 + m + (int64_t)n * ld;
-        if (!bf) {
-          float* C = (float*)tile;
-          C[o] += alpha * acc[x][y][r];
-        } else {
-          uint16_t* Ch = (uint16_t*)tile;
-          Ch[o] = f32_to_bf16(bf16_to_f32(Ch[o]) + alpha * acc[x][y][r]);
-        }
+        for (int r = 0; r < 16; ++r) old[r] = C[(int64_t)(8 * (r >> 2) + (r & 3)) * ld];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) C[(int64_t)(8 * (r >> 2) + (r & 3)) * ld] = old[r] + alpha * acc[x][y][r];
+      } else {
+        uint16_t* Ch = (uint16_t*)tile + ob;
+        uint16_t old[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) old[r] = Ch[(int64_t)(8 * (r >> 2) + (r & 3)) * ld];
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          Ch[(int64_t)(8 * (r >> 2) + (r & 3)) * ld] = f32_to_bf16(bf16_to_f32(old[r]) + alpha * acc[x][y][r]);
       }
+    }
   }
 }
 
@@ -231,17 +239,21 @@ __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* 
               (uint16_t*)smraw);
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
     uint16_t* Ch = (uint16_t*)C + u * BLK + (int64_t)v * BLK * ts;
+    // the 16 values of one row group are loaded before any is stored
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
       const int m = wr * 64 + 16 * x + (lane & 15);
+      uint16_t old[4][4];
 #pragma unroll
       for (int y = 0; y < 4; ++y)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int n = wc * 64 + 16 * y + 4 * (lane >> 4) + r;
-          const int64_t o = m + (int64_t)n * ts;
-          Ch[o] = f32_to_bf16(bf16_to_f32(Ch[o]) - acc[x][y][r]);
-        }
+        for (int r = 0; r < 4; ++r) old[y][r] = Ch[m + (int64_t)(wc * 64 + 16 * y + 4 * (lane >> 4) + r) * ts];
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          Ch[m + (int64_t)(wc * 64 + 16 * y + 4 * (lane >> 4) + r) * ts] =
+              f32_to_bf16(bf16_to_f32(old[y][r]) - acc[x][y][r]);
     }
   } else {
     v16f acc[2][2];
