@@ -123,9 +123,10 @@ exageo_status exageo_set_workspace(exageo_ctx *ctx, void *dev_ptr, size_t bytes)
  * structure keeps double-precision tiles near the diagonal and single or half
  * precision farther out (Section 2.1, Fig. 1(d)) without a rule; here, with
  * the locations in the library's Z-order cut into tiles, c_ij = the Matern
- * correlation (eq. (3) divided by sigma2) at the smallest distance between the
- * bounding boxes of location blocks i and j bounds every |Sigma_ab| / sigma2
- * of tile (i, j), and the tile is
+ * correlation (eq. (3) divided by sigma2) at the smallest distance between a
+ * point of location block i and one of block j is the largest |Sigma_ab| /
+ * sigma2 of tile (i, j) (the distances are computed once per call, or once per
+ * estimation), and the tile is
  *   FP64 when c_ij >= fp64_at_or_above,
  *   BF16 when c_ij < bf16_below and c_ik c_jk < bf16_below for every k < j
  *        (the BF16 update multiplies BF16 roundings of L_ik and L_jk),

@@ -30,7 +30,7 @@ struct Plan {
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
          off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_p32 = 0, off_pbt = 0, off_tag = 0,
          off_tbox = 0, off_pool = 0, off_pidx = 0, off_bli = 0, off_blj = 0, off_corr = 0, off_rtry = 0,
-         off_rnrm = 0, off_fb = 0, off_fstrip = 0, off_fpart = 0, off_fout = 0;
+         off_rnrm = 0, off_fb = 0, off_fstrip = 0, off_fpart = 0, off_fout = 0, off_dmin = 0;
   size_t ptmp_doubles = 0;  // FP64 staging of the inverse (also the kriging blocks)
   int nfisher = 0;          // derivative matrices held for the Fisher information (0, 2 or 3)
   int64_t pool_cap = 0;  // mixed precision: FP64 band tiles the pool can hold
@@ -75,6 +75,7 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
     // the size of the FP64 one
     p.pool_cap = std::min<int64_t>((int64_t)noff, std::max<int64_t>(4 * p.NT, ((int64_t)noff + 1) / 2));
     p.off_corr = take(noff * 8);
+    p.off_dmin = take(noff * 8);  // smallest point distance of every off-diagonal tile
     p.off_rtry = take((size_t)p.npad * 8);  // trial residual of the refinement
     p.off_rnrm = take(4 * 8);
     p.off_pool = take((size_t)std::max<int64_t>(1, p.pool_cap) * tt * 8);
@@ -263,6 +264,9 @@ exageo_status prepare_locations(exageo_ctx* c, const Plan& p, const double* x, c
     // bounding boxes of the location blocks of the tiles, for the precision map
     exg::launch_tile_bbox(at<double>(c, p.off_xs), at<double>(c, p.off_ys), p.ts, p.NT, p.n,
                           at<double>(c, p.off_tbox), c->stream);
+    if (c->metric == EXAGEO_EUCLIDEAN)
+      exg::launch_tile_dmin(at<double>(c, p.off_xs), at<double>(c, p.off_ys), p.ts, p.NT, p.n,
+                            at<double>(c, p.off_dmin), c->stream);
     c->tbox.assign((size_t)p.NT * 4, 0.0);
     HIPCHK(c, hipMemcpyAsync(c->tbox.data(), at<double>(c, p.off_tbox), (size_t)p.NT * 4 * 8, hipMemcpyDeviceToHost,
                              c->stream));
@@ -274,7 +278,7 @@ exageo_status prepare_locations(exageo_ctx* c, const Plan& p, const double* x, c
 // Precision of every off-diagonal tile (TAG_F32, TAG_BF16 or TAG_F64) and the
 // FP64 pool slots, from the tile bounding boxes of the sorted locations.
 //   correlation policy: c_ij = correlation at the smallest distance between
-//     the boxes of location blocks i and j (the tile's largest |Sigma_ab| /
+//     the points of location blocks i and j (the tile's largest |Sigma_ab| /
 //     sigma^2); FP64 when c_ij >= rho64, BF16 when c_ij < rho16 and every
 //     update it receives is small too (max over k < j of c_ik c_jk < rho16:
 //     the BF16 update multiplies BF16 roundings of L_ik and L_jk), FP32
@@ -308,7 +312,7 @@ exageo_status upload_tags(exageo_ctx* c, const Plan& p, const double theta[3], d
       HIPCHK(c, hipHostMalloc((void**)&c->hcorr, noff * 8));
       c->hcorr_words = noff;
     }
-    exg::launch_tile_corr(at<double>(c, p.off_tbox), p.NT, at<double>(c, p.off_qt), at<double>(c, p.off_cst),
+    exg::launch_tile_corr(at<double>(c, p.off_dmin), p.NT, at<double>(c, p.off_qt), at<double>(c, p.off_cst),
                           at<double>(c, p.off_corr), c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->hcorr, at<double>(c, p.off_corr), noff * 8, hipMemcpyDeviceToHost, c->stream));

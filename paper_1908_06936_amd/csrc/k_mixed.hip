@@ -119,23 +119,52 @@ __global__ __launch_bounds__(256) void k_tile_bbox(const double* __restrict__ xs
   if (t < 4) box[4 * k + t] = red[t][0];
 }
 
-// corr[off_index(i, j)] = the Matern correlation at the smallest distance
-// between the bounding boxes of location blocks i > j: an upper bound of
-// |Sigma_ab| / sigma^2 over the tile's entries, since the correlation
-// decreases with distance (planar coordinates only)
-__global__ __launch_bounds__(256) void k_tile_corr(const double* __restrict__ box, int64_t NT,
-                                                   const double* __restrict__ qt, const double* __restrict__ cst,
-                                                   double* __restrict__ corr) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= NT * (NT - 1) / 2) return;
+// dmin[off_index(i, j)] = the smallest distance between a real point of
+// location block i and one of block j, i > j (planar coordinates): one
+// workgroup per tile pair, block j's points staged in LDS, a min-reduction.
+// It depends on the sorted locations only, so an estimation computes it once.
+__global__ __launch_bounds__(256) void k_tile_dmin(const double* __restrict__ xs, const double* __restrict__ ys,
+                                                   int64_t ts, int64_t NT, int64_t nreal, double* __restrict__ dmin) {
+  extern __shared__ double sp[];  // 2 ts: block j's x then y
+  __shared__ double red[256];
+  const int64_t p = blockIdx.x;
   int64_t a, b;
   tri_decode(p, &a, &b);  // b <= a < NT - 1
   const int64_t i = a + 1, j = b;
-  const double* bi = box + 4 * i;
-  const double* bj = box + 4 * j;
-  const double dx = fmax(0.0, fmax(bi[0] - bj[1], bj[0] - bi[1]));
-  const double dy = fmax(0.0, fmax(bi[2] - bj[3], bj[2] - bi[3]));
-  corr[off_index(i, j, NT)] = matern_value(sqrt(dx * dx + dy * dy), cst, qt) / cst[C_S2];
+  const int t = threadIdx.x;
+  const int64_t nj = nreal - j * ts < ts ? nreal - j * ts : ts;
+  const int64_t ni = nreal - i * ts < ts ? nreal - i * ts : ts;
+  for (int64_t q = t; q < nj; q += 256) {
+    sp[q] = xs[j * ts + q];
+    sp[ts + q] = ys[j * ts + q];
+  }
+  __syncthreads();
+  double m = DBL_MAX;
+  for (int64_t q = t; q < ni; q += 256) {
+    const double px = xs[i * ts + q], py = ys[i * ts + q];
+    for (int64_t r = 0; r < nj; ++r) {
+      const double dx = px - sp[r], dy = py - sp[ts + r];
+      m = fmin(m, dx * dx + dy * dy);
+    }
+  }
+  red[t] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmin(red[t], red[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) dmin[off_index(i, j, NT)] = sqrt(red[0]);
+}
+
+// corr[q] = the Matern correlation at distance dmin[q] for every off-diagonal
+// tile: the largest |Sigma_ab| / sigma^2 of the tile, since the correlation
+// decreases with distance
+__global__ __launch_bounds__(256) void k_tile_corr(const double* __restrict__ dmin, int64_t noff,
+                                                   const double* __restrict__ qt, const double* __restrict__ cst,
+                                                   double* __restrict__ corr) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= noff) return;
+  corr[q] = matern_value(dmin[q], cst, qt) / cst[C_S2];
 }
 
 // --------------------------------------------------------- panel staging
@@ -500,11 +529,19 @@ void launch_tile_bbox(const double* xs, const double* ys, int64_t ts, int64_t NT
   hipLaunchKernelGGL(k_tile_bbox, dim3((unsigned)NT), dim3(256), 0, s, xs, ys, ts, nreal, box);
 }
 
-void launch_tile_corr(const double* box, int64_t NT, const double* qt, const double* cst, double* corr,
+void launch_tile_dmin(const double* xs, const double* ys, int64_t ts, int64_t NT, int64_t nreal, double* dmin,
                       hipStream_t s) {
   const int64_t noff = NT * (NT - 1) / 2;
   if (noff <= 0) return;
-  hipLaunchKernelGGL(k_tile_corr, dim3((unsigned)((noff + 255) / 256)), dim3(256), 0, s, box, NT, qt, cst, corr);
+  hipLaunchKernelGGL(k_tile_dmin, dim3((unsigned)noff), dim3(256), (size_t)(2 * ts * sizeof(double)), s, xs, ys, ts,
+                     NT, nreal, dmin);
+}
+
+void launch_tile_corr(const double* dmin, int64_t NT, const double* qt, const double* cst, double* corr,
+                      hipStream_t s) {
+  const int64_t noff = NT * (NT - 1) / 2;
+  if (noff <= 0) return;
+  hipLaunchKernelGGL(k_tile_corr, dim3((unsigned)((noff + 255) / 256)), dim3(256), 0, s, dmin, noff, qt, cst, corr);
 }
 
 void launch_panel_gather(const TileMat& M, int64_t k, const uint8_t* tag, double* pbuf, hipStream_t s) {

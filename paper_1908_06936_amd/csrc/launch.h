@@ -55,9 +55,11 @@ void launch_diag_apply_t(const double* Xk, int64_t ts, const double* b, double* 
 // k_mixed.hip
 void launch_tile_bbox(const double* xs, const double* ys, int64_t ts, int64_t NT, int64_t nreal, double* box,
                       hipStream_t s);
-// corr[off_index(i, j)]: correlation bound of every off-diagonal tile from the
-// location boxes (box: 4 doubles per tile)
-void launch_tile_corr(const double* box, int64_t NT, const double* qt, const double* cst, double* corr,
+// dmin[off_index(i, j)]: smallest distance between the real points of location
+// blocks i > j (sorted, planar); corr: the correlation at that distance
+void launch_tile_dmin(const double* xs, const double* ys, int64_t ts, int64_t NT, int64_t nreal, double* dmin,
+                      hipStream_t s);
+void launch_tile_corr(const double* dmin, int64_t NT, const double* qt, const double* cst, double* corr,
                       hipStream_t s);
 void launch_panel_gather(const TileMat& M, int64_t k, const uint8_t* tag, double* pbuf, hipStream_t s);
 void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const double* pbuf, float* p32,
