@@ -33,10 +33,10 @@ HBM_PEAK_GBS = 8000.0
 # device copy read and write 1 GiB.  Valid only for the kernel source the
 # counters were taken on: the shared GEMM core (common.h) and the text of
 # k_chol_update and of its launcher (fingerprint below); otherwise null.
-TRAFFIC_BYTES_PER_LAUNCH = (4.9520e6 * 2.0 + 1.0333e6 * 1.0) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = (2.4415e6 * 2.0 + 1.0333e6 * 1.0) * 1024
 TRAFFIC_FILES = ("paper_1908_06936_amd/csrc/common.h",)
 TRAFFIC_FUNCTIONS = ("paper_1908_06936_amd/csrc/k_gemm.hip", ("k_chol_update", "launch_chol_update"))
-TRAFFIC_FINGERPRINT = "45f82064a89d612e47dc11f6ab70397c72efead6"
+TRAFFIC_FINGERPRINT = "36362165ddb8f42b677698ae308384b9ecb8fc05"
 
 
 def _function_text(src: str, name: str) -> str:
@@ -450,10 +450,12 @@ def precision_study(args) -> int:
 
 def profile_mixed(args) -> int:
     """A short run to profile under rocprofv3: --profile-steps (l, grad l)
-    evaluations in mixed precision (the library's default map) on the m x m
-    jittered grid (--big-n-side, default 200: n = 40,000), theta = (1,
-    --mle-beta, --profile-nu), tile 768, after one warm-up; one JSON line with
-    the per-phase times and tile fractions."""
+    evaluations in --profile-precision (mixed: the library's default map) on
+    the m x m jittered grid (--big-n-side, default 200: n = 40,000), theta =
+    (1, --mle-beta, --profile-nu), or with --profile-field uniform on the
+    headline workload (n = m^2 uniform points, theta = (1, 0.1, 1.0)), tile
+    768, after one warm-up; one JSON line with the per-phase times and tile
+    fractions."""
     import torch
 
     import inputgen
@@ -461,10 +463,15 @@ def profile_mixed(args) -> int:
 
     dev = torch.device("cuda:0")
     m = args.big_n_side
-    x, y = inputgen.jittered_grid(m, seed=0)
+    if args.profile_field == "uniform":
+        # the headline workload: n = m^2 uniform points, theta = (1, 0.1, 1.0)
+        x, y = inputgen.uniform(m * m, seed=0)
+        th = [1.0, 0.1, 1.0]
+    else:
+        x, y = inputgen.jittered_grid(m, seed=0)
+        th = [1.0, args.mle_beta, args.profile_nu]
     X, Y = torch.as_tensor(x, device=dev), torch.as_tensor(y, device=dev)
     E = torch.as_tensor(inputgen.normals(x.size, seed=0), device=dev)
-    th = [1.0, args.mle_beta, args.profile_nu]
     ctx = exa.Context(ts=768)
     Z = ctx.simulate(X, Y, th, E)
     prec = args.profile_precision
@@ -525,6 +532,7 @@ def main() -> int:
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--profile-nu", type=float, default=0.5)
     ap.add_argument("--profile-precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--profile-field", default="grid", choices=["grid", "uniform"])
     args = ap.parse_args()
 
     if args.copy_calibration:
