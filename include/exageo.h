@@ -212,9 +212,11 @@ exageo_status exageo_loglik(exageo_ctx *ctx, int64_t n, const double *x, const d
                             const double theta[3], int precision, double *loglik, int64_t *info);
 
 /* l(theta) and grad[k] = dl/dtheta_k for theta = (sigma2, beta, nu).
- * EXAGEO_MIXED computes the inverse factor and Sigma^-1 on FP32 MFMA (FP64
- * diagonal tiles, FP32 off-diagonal tiles) after the mixed factorisation; the
- * score sums stay FP64.  On ENOTPD grad is left untouched. */
+ * EXAGEO_MIXED computes the inverse factor and Sigma^-1 after the mixed
+ * factorisation in the precision map of the factor: FP64 diagonal tiles and
+ * FP64 tiles where the factor has its FP64 band (FP64 MFMA), FP32 tiles
+ * elsewhere (FP32 MFMA; BF16 tiles of the factor give FP32 tiles); the score
+ * sums stay FP64.  On ENOTPD grad is left untouched. */
 exageo_status exageo_loglik_grad(exageo_ctx *ctx, int64_t n, const double *x, const double *y,
                                  const double *z, const double theta[3], int precision, double *loglik,
                                  double grad[3], int64_t *info);

@@ -29,7 +29,7 @@ struct Plan {
   size_t off_diag = 0, off_offt = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
          off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_p32 = 0, off_pbt = 0, off_tag = 0,
-         off_tbox = 0, off_pool = 0, off_pidx = 0, off_bli = 0, off_blj = 0, off_corr = 0, off_rtry = 0,
+         off_tbox = 0, off_pool = 0, off_pidx = 0, off_bli = 0, off_blj = 0, off_brl = 0, off_corr = 0, off_rtry = 0,
          off_rnrm = 0, off_fb = 0, off_fstrip = 0, off_fpart = 0, off_fout = 0, off_dmin = 0;
   size_t ptmp_doubles = 0;  // FP64 staging of the inverse (also the kriging blocks)
   int nfisher = 0;          // derivative matrices held for the Fisher information (0, 2 or 3)
@@ -82,6 +82,7 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
     p.off_pidx = take(noff * 4);
     p.off_bli = take((size_t)std::max<int64_t>(1, p.pool_cap) * 4);
     p.off_blj = take((size_t)std::max<int64_t>(1, p.pool_cap) * 4);
+    p.off_brl = take((size_t)std::max<int64_t>(1, p.pool_cap) * 4);  // band list entries by tile rows
   }
   p.off_xd = take((size_t)p.NT * tt * 8);
   // FP64 inverse: FP64 staging buffer (the mixed inverse stages in the FP32 panel copy)
@@ -167,9 +168,11 @@ struct exageo_ctx {
   size_t hcorr_words = 0;
   // FP64 band: pool slot per off-diagonal tile, band list (column-major
   // order) and the first list entry of each tile column, all host copies
-  int32_t* hband = nullptr;  // pinned: pidx (noff) then li, lj (pool_cap each)
+  int32_t* hband = nullptr;  // pinned: pidx (noff) then li, lj, rl (pool_cap each)
   size_t hband_words = 0;
   std::vector<int64_t> bfirst;
+  // the same list by tile rows: rl[r] = list entry, rfirst[i] = first r of row i
+  std::vector<int64_t> brfirst;
   // side stream (default priority) for the lookahead panel, and its events
   hipStream_t side = nullptr;
   hipEvent_t ev_col = nullptr, ev_panel = nullptr;
@@ -290,7 +293,7 @@ exageo_status prepare_locations(exageo_ctx* c, const Plan& p, const double* x, c
 // off-diagonal tile is FP32.  Returns the BF16 and FP64 fractions.
 exageo_status upload_tags(exageo_ctx* c, const Plan& p, const double theta[3], double* frac_bf16, double* frac_fp64) {
   const size_t noff = (size_t)std::max<int64_t>(1, p.NT * (p.NT - 1) / 2);
-  const size_t words = noff + 2 * (size_t)std::max<int64_t>(1, p.pool_cap);
+  const size_t words = noff + 3 * (size_t)std::max<int64_t>(1, p.pool_cap);
   if (c->htag_bytes < noff) {
     if (c->htag) HIPCHK(c, hipHostFree(c->htag));
     c->htag = nullptr;
@@ -379,6 +382,15 @@ exageo_status upload_tags(exageo_ctx* c, const Plan& p, const double theta[3], d
     }
   }
   c->bfirst[p.NT] = nb64;
+  // row order: count per row, prefix sums, then entries in column order within a row
+  int32_t* rl = lj + std::max<int64_t>(1, p.pool_cap);
+  c->brfirst.assign((size_t)p.NT + 1, 0);
+  for (int64_t e = 0; e < nb64; ++e) ++c->brfirst[(size_t)li[e] + 1];
+  for (int64_t i = 0; i < p.NT; ++i) c->brfirst[(size_t)i + 1] += c->brfirst[(size_t)i];
+  {
+    std::vector<int64_t> fill(c->brfirst.begin(), c->brfirst.end() - 1);
+    for (int64_t e = 0; e < nb64; ++e) rl[fill[(size_t)li[e]]++] = (int32_t)e;
+  }
   if (p.NT == 1) {
     c->htag[0] = exg::TAG_F32;
     pidx[0] = -1;
@@ -388,6 +400,7 @@ exageo_status upload_tags(exageo_ctx* c, const Plan& p, const double theta[3], d
   if (nb64 > 0) {
     HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_bli), li, (size_t)nb64 * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_blj), lj, (size_t)nb64 * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_brl), rl, (size_t)nb64 * 4, hipMemcpyHostToDevice, c->stream));
   }
   *frac_bf16 = ntot ? (double)nbf / (double)ntot : 0.0;
   *frac_fp64 = ntot ? (double)nb64 / (double)ntot : 0.0;
@@ -619,15 +632,23 @@ exageo_status gradient(exageo_ctx* c, const Plan& p) {
   exg::launch_copy(rhs, at<double>(c, p.off_y), p.npad, c->stream);
   exageo_status st;
   if (p.mixed) {
-    // mixed precision: the same steps with FP32 off-diagonal tiles of L^-1
-    // (staged in the two halves of the FP32 panel copy)
+    // mixed precision: the same steps with the off-diagonal tiles of L^-1 in
+    // FP64 on the factor's FP64 band and FP32 elsewhere (staged in the two
+    // halves of the FP32 panel copy and of the FP64 panel buffer)
     const uint8_t* tag = at<uint8_t>(c, p.off_tag);
     float* P32 = at<float>(c, p.off_p32);
+    double* Q64 = at<double>(c, p.off_pbuf);
+    const exg::BandLists bl{at<int32_t>(c, p.off_bli), at<int32_t>(c, p.off_blj), at<int32_t>(c, p.off_brl),
+                            c->bfirst.data(), c->brfirst.data()};
     if (c->refine <= 0) exg::launch_trsv_bwd_lp(M, tag, Xd, rhs, av, c->stream);
     st = trtri_two_streams(
         c, p.NT,
-        [&](int64_t k, hipStream_t s) { exg::launch_trtri_right_lp(M, tag, Xd + k * tt, P32 + (k & 1) * half, k, p.n, s); },
-        [&](int64_t k, hipStream_t s) { exg::launch_trtri_rest_lp(M, Xd + k * tt, P32 + (k & 1) * half, k, p.n, s); });
+        [&](int64_t k, hipStream_t s) {
+          exg::launch_trtri_right_lp(M, tag, Xd + k * tt, P32 + (k & 1) * half, Q64 + (k & 1) * half, bl, k, p.n, s);
+        },
+        [&](int64_t k, hipStream_t s) {
+          exg::launch_trtri_rest_lp(M, tag, Xd + k * tt, P32 + (k & 1) * half, Q64 + (k & 1) * half, bl, k, p.n, s);
+        });
     if (st) return st;
     nparts = exg::launch_lauum_contract_lp(M, tag, p.n, at<double>(c, p.off_xs), at<double>(c, p.off_ys), av,
                                            at<double>(c, p.off_qt), at<double>(c, p.off_cst),

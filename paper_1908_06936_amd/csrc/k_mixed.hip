@@ -355,11 +355,130 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_gemv_bwd_lp(TileMat M, const 
   }
 }
 
+// ------------------------------------- FP64 MFMA core over mixed operands
+// gemm_core's block product (same lane layout, stages, double buffering and
+// order of the products) for operands whose element type changes along k:
+// aptr(k0) / bptr(k0) return the address of Op(0, k0) for one BK-deep stage
+// and whether the elements there are FP64 or FP32 (uniform over the
+// workgroup; FP32 widened exactly at the LDS store).  One instantiation covers
+// every mix, which keeps a kernel with several tile precisions to one copy of
+// the k loop.
+struct MixPtr {
+  const void* p;
+  bool f64;
+};
+
+template <bool AKC, bool BKC, class AP, class BP>
+__device__ __forceinline__ void gemm_core_mix(AP aptr, int64_t lda, BP bptr, int64_t ldb, int K, v4d (&acc)[4][4],
+                                              double* sm) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  double* sA = sm;
+  double* sB = sm + 2 * BK * LDP;
+  // a register set: four element pairs per operand, raw (two doubles, or two
+  // floats in the first 8 bytes) and the element type of the stage
+  struct Set {
+    uint4 a[4], b[4];
+    bool fa, fb;
+  };
+  Set r0, r1;
+  auto eoff = [&](bool kc, int idx, int64_t ld) -> int64_t {
+    return kc ? 2 * (idx & 7) + (int64_t)(idx >> 3) * ld : 2 * (idx & 63) + (int64_t)(idx >> 6) * ld;
+  };
+  auto gload = [&](int k0, Set& r) {
+    const MixPtr A = aptr(k0), B = bptr(k0);
+    r.fa = A.f64;
+    r.fb = B.f64;
+    if (A.f64) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) r.a[s] = *(const uint4*)((const double*)A.p + eoff(AKC, t + GEMM_THREADS * s, lda));
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const uint2 f = *(const uint2*)((const float*)A.p + eoff(AKC, t + GEMM_THREADS * s, lda));
+        r.a[s].x = f.x, r.a[s].y = f.y;
+      }
+    }
+    if (B.f64) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) r.b[s] = *(const uint4*)((const double*)B.p + eoff(BKC, t + GEMM_THREADS * s, ldb));
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const uint2 f = *(const uint2*)((const float*)B.p + eoff(BKC, t + GEMM_THREADS * s, ldb));
+        r.b[s].x = f.x, r.b[s].y = f.y;
+      }
+    }
+  };
+  auto widen = [](const uint4& u, bool f64) -> d2 {
+    if (f64) return (d2){__hiloint2double((int)u.y, (int)u.x), __hiloint2double((int)u.w, (int)u.z)};
+    return (d2){(double)__uint_as_float(u.x), (double)__uint_as_float(u.y)};
+  };
+  auto put = [&](double* S, bool kc, int idx, d2 v) {
+    if (!kc) {
+      *(d2*)(S + (idx >> 6) * LDP + 2 * (idx & 63)) = v;
+    } else {
+      const int m = idx >> 3, kp = idx & 7;
+      S[(2 * kp) * LDP + m] = v.x;
+      S[(2 * kp + 1) * LDP + m] = v.y;
+    }
+  };
+  auto sstore = [&](int buf, const Set& r) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int idx = t + GEMM_THREADS * s;
+      put(sA + buf * BK * LDP, AKC, idx, widen(r.a[s], r.fa));
+      put(sB + buf * BK * LDP, BKC, idx, widen(r.b[s], r.fb));
+    }
+  };
+  auto compute = [&](int cur) {
+    const double* a = sA + cur * BK * LDP + wr * 64 + (lane & 15);
+    const double* b = sB + cur * BK * LDP + wc * 64 + (lane & 15);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int ko = (kk + (lane >> 4)) * LDP;
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = a[ko + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = b[ko + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(bf[j], af[i], acc[i][j]);
+    }
+  };
+  const int nst = K / BK;  // even
+  gload(0, r0);
+  gload(BK, r1);
+  sstore(0, r0);
+  __syncthreads();
+  for (int st = 0; st < nst; st += 2) {
+    if (st + 2 < nst) gload((st + 2) * BK, r0);
+    compute(0);
+    sstore(1, r1);
+    __syncthreads();
+    if (st + 3 < nst) gload((st + 3) * BK, r1);
+    compute(1);
+    if (st + 2 < nst) sstore(0, r0);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------ mixed tile TRTRI, step k
-// The same four steps as the FP64 inverse, with every off-diagonal tile of
-// L^-1 held in FP32 (the 4-byte slots take FP32 whatever the tile's tag was:
-// a tile is read through its tag only as an untouched factor tile, in the
-// first step below, and is FP32 from then on) and every product on FP32 MFMA.
+// The same four steps as the FP64 inverse.  L^-1 follows the precision map of
+// the factor: a tile of the FP64 band (tag FP64) stays FP64 in its pool slot,
+// every product into it runs on FP64 MFMA (FP32 operands widened exactly), and
+// its FP32 rounding is kept in the tile's 4-byte slot for the FP32 readers of
+// the finished inverse; every other off-diagonal tile is FP32 (the 4-byte
+// slots take FP32 whatever the tile's tag was: a tile is read through its tag
+// only as an untouched factor tile, in the first step below, and is FP32 from
+// then on) with its products on FP32 MFMA.  The band tiles carry the largest
+// entries of L^-1, and their FP32 sums were the main error of the score's
+// trace term.  The FP32 kernels below skip band targets; the *_band kernels
+// take them, staging in the FP64 buffer Q (same tile positions as P) and
+// writing the FP32 rounding into P, so that P stays complete for the FP32
+// readers.
 // P_i = -L_ik X_kk for i > k into the FP32 buffer P (tile i - k - 1); k range
 // restricted to the non-zero rows v*128.. of the lower-triangular X_kk.
 __global__ __launch_bounds__(256, 2) void k_tri_right_lp(TileMat M, const uint8_t* __restrict__ tag,
@@ -373,19 +492,18 @@ __global__ __launch_bounds__(256, 2) void k_tri_right_lp(TileMat M, const uint8_
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
   const int64_t off = (int64_t)v * BLK * ts;
+  const int64_t idx = off_index(i, k, M.NT);
+  const int tg = tag[idx];
+  if (tg == TAG_F64) return;  // k_tri_right_band
   float* C = P + (i - k - 1) * tt + u * BLK + off;
   v16f acc[2][2];
   acc32_zero(acc);
   // padded rows of L^-1 are zero: store zeros (the buffer is copied back whole)
   if (i * ts + u * BLK < nreal) {
-    const int64_t idx = off_index(i, k, M.NT);
     const float* A = (const float*)M.off + idx * tt;
     const double* B = Xk + v * BLK + off;
     const int K = (int)(ts - v * BLK);
-    const int tg = tag[idx];
-    if (tg == TAG_F64)
-      gemm32_blk<SRC_F64, false, SRC_F64, true>(band64(M, idx) + u * BLK + off, ts, B, ts, K, acc, sm);
-    else if (tg == TAG_BF16)
+    if (tg == TAG_BF16)
       gemm32_blk<SRC_BF16, false, SRC_F64, true>((const uint16_t*)A + u * BLK + off, ts, B, ts, K, acc, sm);
     else
       gemm32_blk<SRC_F32, false, SRC_F64, true>(A + u * BLK + off, ts, B, ts, K, acc, sm);
@@ -393,9 +511,11 @@ __global__ __launch_bounds__(256, 2) void k_tri_right_lp(TileMat M, const uint8_
   acc32_store(C, ts, acc, -1.f);
 }
 
-// A_ij += P_i A_kj for k < i < NT, 0 <= j < k (P_i = the new A_ik)
-__global__ __launch_bounds__(256, 2) void k_tri_gemm_lp(TileMat M, const float* __restrict__ P, int T, int64_t k,
-                                                        int64_t nreal, int64_t nb) {
+// A_ij += P_i A_kj for k < i < NT, 0 <= j < k (P_i = the new A_ik), FP32
+// targets; A_kj of a band tile is read from its FP64 slot
+__global__ __launch_bounds__(256, 2) void k_tri_gemm_lp(TileMat M, const uint8_t* __restrict__ tag,
+                                                        const float* __restrict__ P, int T, int64_t k, int64_t nreal,
+                                                        int64_t nb) {
   __shared__ float sm[G32_LDS];
   const int64_t ts = M.ts, tt = ts * ts;
   const int64_t b = blockIdx.x;
@@ -404,23 +524,30 @@ __global__ __launch_bounds__(256, 2) void k_tri_gemm_lp(TileMat M, const float* 
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
   const int64_t i = k + 1 + p / k, j = p % k;
-  if (i * ts + u * BLK >= nreal) return;
+  if (i * ts + u * BLK >= nreal || tag[off_index(i, j, M.NT)] == TAG_F64) return;
   v16f acc[2][2];
   acc32_zero(acc);
-  gemm32_blk<SRC_F32, false, SRC_F32, true>(P + (i - k - 1) * tt + u * BLK, ts, off32(M, k, j) + (int64_t)v * BLK * ts,
-                                            ts, (int)ts, acc, sm);
-  acc32_update(off32(M, i, j), false, u * BLK + (int64_t)v * BLK * ts, ts, acc, 1.f);
+  const float* A = P + (i - k - 1) * tt + u * BLK;
+  const int64_t kj = off_index(k, j, M.NT), ob = (int64_t)v * BLK * ts;
+  if (tag[kj] == TAG_F64)
+    gemm32_blk<SRC_F32, false, SRC_F64, true>(A, ts, band64(M, kj) + ob, ts, (int)ts, acc, sm);
+  else
+    gemm32_blk<SRC_F32, false, SRC_F32, true>(A, ts, off32(M, k, j) + ob, ts, (int)ts, acc, sm);
+  acc32_update(off32(M, i, j), false, u * BLK + ob, ts, acc, 1.f);
 }
 
 // R_j = X_kk A_kj for j < k into the FP32 buffer P (tile j); k range
 // restricted to the non-zero columns ..(u+1)*128 of row block u of X_kk.
-__global__ __launch_bounds__(256, 2) void k_tri_left_lp(TileMat M, const double* __restrict__ Xk,
-                                                        float* __restrict__ P, int T, int64_t k, int64_t nb) {
+// Band tiles (k, j) are left to k_tri_left_band.
+__global__ __launch_bounds__(256, 2) void k_tri_left_lp(TileMat M, const uint8_t* __restrict__ tag,
+                                                        const double* __restrict__ Xk, float* __restrict__ P, int T,
+                                                        int64_t k, int64_t nb) {
   __shared__ float sm[G32_LDS];
   const int64_t ts = M.ts, tt = ts * ts;
   const int64_t b = blockIdx.x;
   if (b >= nb) return;
   const int64_t j = b / (T * T);
+  if (tag[off_index(k, j, M.NT)] == TAG_F64) return;
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
   const int64_t off = (int64_t)v * BLK * ts;
@@ -428,6 +555,121 @@ __global__ __launch_bounds__(256, 2) void k_tri_left_lp(TileMat M, const double*
   acc32_zero(acc);
   gemm32_blk<SRC_F64, false, SRC_F32, true>(Xk + u * BLK, ts, off32(M, k, j) + off, ts, (u + 1) * BLK, acc, sm);
   acc32_store(P + j * tt + u * BLK + off, ts, acc, 1.f);
+}
+
+// C = alpha acc into a 128 x 128 block of an FP64 array and its FP32 rounding
+// into the same place of an FP32 array (acc_store's lane assignment)
+__device__ __forceinline__ void acc_store_pair(double* C, float* C32, int64_t ldc, const v4d (&acc)[4][4],
+                                               double alpha) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = wr * 64 + 16 * i + (lane & 15);
+    const int64_t o = m + (int64_t)(wc * 64 + (lane >> 4)) * ldc;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double v = alpha * acc[i][j][r];
+        const int64_t e = o + (int64_t)(16 * j + 4 * r) * ldc;
+        C[e] = v;
+        C32[e] = (float)v;
+      }
+  }
+}
+
+// Band tiles of column k: P_i = -L_ik X_kk on FP64 MFMA for the list entries
+// e0 + q (tile (li[e0 + q], k)), into Q and its FP32 rounding into P.
+__global__ __launch_bounds__(256, 2) void k_tri_right_band(TileMat M, const double* __restrict__ Xk,
+                                                           double* __restrict__ Q, float* __restrict__ P,
+                                                           const int32_t* __restrict__ li, int64_t e0, int T,
+                                                           int64_t k, int64_t nreal, int64_t nb) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t ts = M.ts, tt = ts * ts;
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const int64_t i = li[e0 + b / (T * T)];
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  const int64_t off = (int64_t)v * BLK * ts, o = (i - k - 1) * tt + u * BLK + off;
+  v4d acc[4][4];
+  acc_zero(acc);
+  if (i * ts + u * BLK < nreal)
+    gemm_blk<false, true>(band64(M, off_index(i, k, M.NT)) + u * BLK + off, ts, Xk + v * BLK + off, ts,
+                          (int)(ts - v * BLK), acc, sm);
+  acc_store_pair(Q + o, P + o, ts, acc, -1.0);
+}
+
+// Band targets of step k: A_ij += P_i A_kj for the list entries e < e1 (the
+// band tiles of columns j < k) with li[e] > k, on FP64 MFMA; P_i from Q where
+// (i, k) is a band tile, else from P, and A_kj from the FP64 slot where (k, j)
+// is a band tile, else from the FP32 slot.
+__global__ __launch_bounds__(256, 2) void k_tri_gemm_band(TileMat M, const uint8_t* __restrict__ tag,
+                                                          const double* __restrict__ Q, const float* __restrict__ P,
+                                                          const int32_t* __restrict__ li,
+                                                          const int32_t* __restrict__ lj, int T, int64_t k,
+                                                          int64_t nreal, int64_t nb) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t ts = M.ts, tt = ts * ts, NT = M.NT;
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const int64_t e = b / (T * T);
+  const int64_t i = li[e], j = lj[e];
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  if (i <= k || i * ts + u * BLK >= nreal) return;
+  v4d acc[4][4];
+  acc_zero(acc);
+  const int64_t oa = (i - k - 1) * tt + u * BLK, ob = (int64_t)v * BLK * ts;
+  const int64_t kj = off_index(k, j, NT);
+  const bool a64 = tag[off_index(i, k, NT)] == TAG_F64, b64 = tag[kj] == TAG_F64;
+  // byte addresses and log2 of the element size of both operands
+  const char* A = a64 ? (const char*)(Q + oa) : (const char*)(P + oa);
+  const char* B = b64 ? (const char*)(band64(M, kj) + ob) : (const char*)(off32(M, k, j) + ob);
+  const int sa = a64 ? 3 : 2, sb = b64 ? 3 : 2;
+  gemm_core_mix<false, true>([=](int k0) { return MixPtr{A + (((int64_t)k0 * ts) << sa), a64}; }, ts,
+                             [=](int k0) { return MixPtr{B + ((int64_t)k0 << sb), b64}; }, ts, (int)ts, acc, sm);
+  acc_store(band64(M, off_index(i, j, NT)) + u * BLK + ob, ts, acc, 1.0, true);
+}
+
+// Band tiles of row k: R_j = X_kk A_kj on FP64 MFMA for the row-list entries
+// rl[r0 + q] (tile (k, lj[.])), into Q and its FP32 rounding into P (tile j).
+__global__ __launch_bounds__(256, 2) void k_tri_left_band(TileMat M, const double* __restrict__ Xk,
+                                                          double* __restrict__ Q, float* __restrict__ P,
+                                                          const int32_t* __restrict__ lj,
+                                                          const int32_t* __restrict__ rl, int64_t r0, int T,
+                                                          int64_t k, int64_t nb) {
+  __shared__ double sm[GEMM_LDS];
+  const int64_t ts = M.ts, tt = ts * ts;
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const int64_t j = lj[rl[r0 + b / (T * T)]];
+  const int sub = (int)(b % (T * T));
+  const int u = sub / T, v = sub % T;
+  const int64_t off = (int64_t)v * BLK * ts, o = j * tt + u * BLK + off;
+  v4d acc[4][4];
+  acc_zero(acc);
+  gemm_blk<false, true>(Xk + u * BLK, ts, band64(M, off_index(k, j, M.NT)) + off, ts, (u + 1) * BLK, acc, sm);
+  acc_store_pair(Q + o, P + o, ts, acc, 1.0);
+}
+
+// FP64 slots of band tiles <- Q: column mode, tiles (li[e0 + q], k) from Q tile
+// li - k - 1; row mode, tiles (k, lj[rl[e0 + q]]) from Q tile lj; q < count
+__global__ void k_copy_back_band(TileMat M, const double* __restrict__ Q, const int32_t* __restrict__ li,
+                                 const int32_t* __restrict__ lj, const int32_t* __restrict__ rl, int64_t e0,
+                                 int64_t count, int64_t k, int column) {
+  const int64_t tt = M.ts * M.ts;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count * tt) return;
+  const int64_t q = e / tt, o = e % tt;
+  int64_t i, j, src;
+  if (column) {
+    i = li[e0 + q], j = k, src = i - k - 1;
+  } else {
+    i = k, j = lj[rl[e0 + q]], src = j;
+  }
+  band64(M, off_index(i, j, M.NT))[o] = Q[src * tt + o];
 }
 
 // FP32 tile (i0 + q, jcol) or (irow, j0 + q) <- P tile q, q < count
@@ -441,12 +683,58 @@ __global__ void k_copy_back_lp(TileMat M, const float* __restrict__ P, int64_t c
   off32(M, i, j)[o] = P[e];
 }
 
+// ------------------------------------------ tile transposition (mixed)
+// Every lower tile of X = L^-1 in mixed storage (FP64 diagonal tiles, FP32
+// off-diagonal slots, FP64 band slots) transposed in place, as the FP64 path
+// does, so that both LAUUM operands are read along their contiguous index.
+// One workgroup swaps the 64 x 64 blocks (a, b) and (b, a), a <= b, of one
+// tile through LDS.
+template <typename E>
+__device__ __forceinline__ void swap_blocks64(E* T, int64_t ts, int64_t ra, int64_t rb, bool same, E (*s1)[65],
+                                              E (*s2)[65]) {
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    s1[c][r] = T[(ra + r) + (rb + c) * ts];
+    if (!same) s2[c][r] = T[(rb + r) + (ra + c) * ts];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    if (!same) {
+      T[(ra + r) + (rb + c) * ts] = s2[r][c];
+      T[(rb + r) + (ra + c) * ts] = s1[r][c];
+    } else {
+      T[(ra + r) + (ra + c) * ts] = s1[r][c];
+    }
+  }
+}
+
+// blocks g < nlow: the lower tiles in tile order; g >= nlow: the band pool slots
+__global__ __launch_bounds__(256) void k_transpose_tiles_lp(TileMat M, int64_t npt, int64_t nlow, int64_t nb) {
+  __shared__ double d1[64][65], d2[64][65];
+  const int64_t g = blockIdx.x;
+  if (g >= nb) return;
+  int64_t I, J, bq, aq;
+  tri_decode(g % npt, &bq, &aq);  // aq <= bq
+  if (g >= nlow) {
+    swap_blocks64<double>(M.pool + (g - nlow) / npt * M.ts * M.ts, M.ts, aq * 64, bq * 64, aq == bq, d1, d2);
+    return;
+  }
+  tri_decode(g / npt, &I, &J);
+  if (I == J)
+    swap_blocks64<double>(M.diag + I * M.ts * M.ts, M.ts, aq * 64, bq * 64, aq == bq, d1, d2);
+  else
+    swap_blocks64<float>(off32(M, I, J), M.ts, aq * 64, bq * 64, aq == bq, (float(*)[65])d1, (float(*)[65])d2);
+}
+
 // ------------------------------------ mixed fused LAUUM + score contraction
-// X = L^-1 has FP64 diagonal tiles and FP32 off-diagonal tiles.  W follows the
-// precision map of Sigma: blocks W_IJ of FP32 and BF16 tiles run on FP32 MFMA
-// with FP32 accumulation; diagonal blocks W_II and the blocks of FP64 band
-// tiles run on FP64 MFMA (FP32 tiles widened exactly), where the entries of
-// dSigma are largest.  The contraction is FP64 in both.
+// X = L^-1 has FP64 diagonal tiles and FP32 off-diagonal tiles, every tile
+// transposed by k_transpose_tiles_lp: the stored T(K, I) holds X(K, I)^T, so
+// X(K, I)[k, m] = T(K, I)[m + k ts] and both operands of
+// W_IJ = sum_K X_KI^T X_KJ are read along their contiguous index.  W follows the precision map of Sigma: blocks W_IJ of FP32 and BF16
+// tiles run on FP32 MFMA with FP32 accumulation; diagonal blocks W_II and the
+// blocks of FP64 band tiles run on FP64 MFMA (FP32 tiles widened exactly),
+// where the entries of dSigma are largest.  The contraction is FP64 in both.
 // FP32 kernel: pair p -> (a, c), c <= a, I = a + 1 > J = c; band tiles skipped.
 __global__ __launch_bounds__(256, 2) void k_lauum_contract_lp(TileMat M, const uint8_t* __restrict__ tag, int T,
                                                               int64_t nreal, const double* __restrict__ xs,
@@ -473,20 +761,23 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract_lp(TileMat M, const u
   acc32_zero(acc);
   const int64_t r0 = (int64_t)u * BLK, c0 = (int64_t)v * BLK;
   // K = I: rows r0.. of the lower-triangular X_II against the same rows of X_IJ
-  gemm32_blk<SRC_F64, true, SRC_F32, true>(M.diag + I * ts * ts + r0 + r0 * ts, ts, off32(M, I, J) + r0 + c0 * ts, ts,
-                                           (int)(ts - r0), acc, sm);
+  gemm32_blk<SRC_F64, false, SRC_F32, false>(M.diag + I * ts * ts + r0 + r0 * ts, ts, off32(M, I, J) + c0 + r0 * ts,
+                                             ts, (int)(ts - r0), acc, sm);
   // K = I + 1 .. NT - 1: every row of the tiles below
   if (I + 1 < NT) {
-    auto ap = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, I) + (k0 % ts) + r0 * ts; };
-    auto bp = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, J) + (k0 % ts) + c0 * ts; };
-    gemm32<SRC_F32, true, SRC_F32, true>(ap, ts, bp, ts, (int)((NT - 1 - I) * ts), acc, sm);
+    auto ap = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, I) + r0 + (int64_t)(k0 % ts) * ts; };
+    auto bp = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, J) + c0 + (int64_t)(k0 % ts) * ts; };
+    gemm32<SRC_F32, false, SRC_F32, false>(ap, ts, bp, ts, (int)((NT - 1 - I) * ts), acc, sm);
   }
   contract_block32(acc, I * ts + r0, J * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
 }
 
 // FP64 kernel: block (I, J, u, v) with (I, J) = the diagonal tile p for
-// p < NT, else band tile (li, lj)[p - NT]; v <= u on the diagonal.
-__global__ __launch_bounds__(256, 2) void k_lauum_f64_lp(TileMat M, int T, int64_t nreal, const double* __restrict__ xs,
+// p < NT, else band tile (li, lj)[p - NT]; v <= u on the diagonal.  X tiles
+// of the band are read from their FP64 slots, the others from their FP32
+// slots (widened), over runs of tiles K with the same pair of precisions.
+__global__ __launch_bounds__(256, 2) void k_lauum_f64_lp(TileMat M, const uint8_t* __restrict__ tag, int T,
+                                                         int64_t nreal, const double* __restrict__ xs,
                                                          const double* __restrict__ ys,
                                                          const double* __restrict__ av,
                                                          const double* __restrict__ qt,
@@ -509,16 +800,17 @@ __global__ __launch_bounds__(256, 2) void k_lauum_f64_lp(TileMat M, int T, int64
   acc_zero(acc);
   const int64_t r0 = (int64_t)u * BLK, c0 = (int64_t)v * BLK;
   const double* XII = M.diag + I * ts * ts;
-  if (I == J)
-    gemm_blk<true, true>(XII + r0 + r0 * ts, ts, XII + r0 + c0 * ts, ts, (int)(ts - r0), acc, sm);
-  else
-    gemm_core<true, true>([=](int k0) -> const double* { return XII + r0 + k0 + r0 * ts; }, ts,
-                          [=](int k0) -> const float* { return off32(M, I, J) + r0 + k0 + c0 * ts; }, ts,
-                          (int)(ts - r0), acc, sm);
+  const double* XIJ = I == J ? XII : band64(M, off_index(I, J, NT));
+  gemm_blk<false, false>(XII + r0 + r0 * ts, ts, XIJ + c0 + r0 * ts, ts, (int)(ts - r0), acc, sm);
+  // K = I + 1 .. NT - 1: each stage lies in one tile K, read in that tile's precision
   if (I + 1 < NT) {
-    auto ap = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, I) + (k0 % ts) + r0 * ts; };
-    auto bp = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, J) + (k0 % ts) + c0 * ts; };
-    gemm_core<true, true>(ap, ts, bp, ts, (int)((NT - 1 - I) * ts), acc, sm);
+    auto op = [=](int k0, int64_t C, int64_t c) {
+      const int64_t idx = off_index(I + 1 + k0 / ts, C, NT), o = c + (int64_t)(k0 % ts) * ts;
+      if (tag[idx] == TAG_F64) return MixPtr{band64(M, idx) + o, true};
+      return MixPtr{(const float*)M.off + idx * ts * ts + o, false};
+    };
+    gemm_core_mix<false, false>([=](int k0) { return op(k0, I, r0); }, ts, [=](int k0) { return op(k0, J, c0); }, ts,
+                                (int)((NT - 1 - I) * ts), acc, sm);
   }
   contract_block64(acc, I * ts + r0, J * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
 }
@@ -613,32 +905,55 @@ void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, 
 }
 
 // the step's two halves for two streams, as launch_trtri_right / _rest
-void launch_trtri_right_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k,
-                           int64_t nreal, hipStream_t s) {
-  const int64_t ts = M.ts, NT = M.NT;
+void launch_trtri_right_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, double* Q,
+                           const BandLists& bl, int64_t k, int64_t nreal, hipStream_t s) {
+  const int64_t ts = M.ts, NT = M.NT, tt = ts * ts;
   const int T = (int)(ts / BLK);
   const int64_t nbelow = NT - k - 1;
   if (nbelow <= 0) return;
   const int64_t nr = nbelow * T * T;
   hipLaunchKernelGGL(k_tri_right_lp, dim3((unsigned)nr), dim3(256), 0, s, M, tag, Xk, P, T, k, nreal, nr);
-  hipLaunchKernelGGL(k_copy_back_lp, dim3((unsigned)((nbelow * ts * ts + 255) / 256)), dim3(256), 0, s, M, P, nbelow,
+  const int64_t e0 = bl.cfirst[k], ne = bl.cfirst[k + 1] - e0;  // band tiles of column k
+  if (ne > 0) {
+    const int64_t nbb = ne * T * T;
+    hipLaunchKernelGGL(k_tri_right_band, dim3((unsigned)nbb), dim3(256), 0, s, M, Xk, Q, P, bl.li, e0, T, k, nreal,
+                       nbb);
+  }
+  hipLaunchKernelGGL(k_copy_back_lp, dim3((unsigned)((nbelow * tt + 255) / 256)), dim3(256), 0, s, M, P, nbelow,
                      k + 1, k, 1);
+  if (ne > 0)
+    hipLaunchKernelGGL(k_copy_back_band, dim3((unsigned)((ne * tt + 255) / 256)), dim3(256), 0, s, M, Q, bl.li,
+                       bl.lj, bl.rl, e0, ne, k, 1);
 }
 
-void launch_trtri_rest_lp(const TileMat& M, const double* Xk, float* P, int64_t k, int64_t nreal, hipStream_t s) {
+void launch_trtri_rest_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, double* Q,
+                          const BandLists& bl, int64_t k, int64_t nreal, hipStream_t s) {
   const int64_t ts = M.ts, NT = M.NT;
   const int T = (int)(ts / BLK);
   const int64_t tt = ts * ts;
   const int64_t nbelow = NT - k - 1;
   if (nbelow > 0 && k > 0) {
     const int64_t ng = nbelow * k * T * T;
-    hipLaunchKernelGGL(k_tri_gemm_lp, dim3((unsigned)ng), dim3(256), 0, s, M, P, T, k, nreal, ng);
+    hipLaunchKernelGGL(k_tri_gemm_lp, dim3((unsigned)ng), dim3(256), 0, s, M, tag, P, T, k, nreal, ng);
+    const int64_t nbg = bl.cfirst[k] * T * T;  // band tiles of columns < k (those with rows > k are targets)
+    if (nbg > 0)
+      hipLaunchKernelGGL(k_tri_gemm_band, dim3((unsigned)nbg), dim3(256), 0, s, M, tag, Q, P, bl.li, bl.lj, T, k,
+                         nreal, nbg);
   }
   if (k > 0) {
     const int64_t nl = k * T * T;
-    hipLaunchKernelGGL(k_tri_left_lp, dim3((unsigned)nl), dim3(256), 0, s, M, Xk, P, T, k, nl);
+    hipLaunchKernelGGL(k_tri_left_lp, dim3((unsigned)nl), dim3(256), 0, s, M, tag, Xk, P, T, k, nl);
+    const int64_t r0 = bl.rfirst[k], nrow = bl.rfirst[k + 1] - r0;  // band tiles of row k
+    if (nrow > 0) {
+      const int64_t nbl = nrow * T * T;
+      hipLaunchKernelGGL(k_tri_left_band, dim3((unsigned)nbl), dim3(256), 0, s, M, Xk, Q, P, bl.lj, bl.rl, r0, T, k,
+                         nbl);
+    }
     hipLaunchKernelGGL(k_copy_back_lp, dim3((unsigned)((k * tt + 255) / 256)), dim3(256), 0, s, M, P, k, k,
                        (int64_t)0, 0);
+    if (nrow > 0)
+      hipLaunchKernelGGL(k_copy_back_band, dim3((unsigned)((nrow * tt + 255) / 256)), dim3(256), 0, s, M, Q, bl.li,
+                         bl.lj, bl.rl, r0, nrow, k, 0);
   }
   launch_copy(M.diag + k * tt, Xk, tt, s);
 }
@@ -651,10 +966,13 @@ int64_t launch_lauum_contract_lp(const TileMat& M, const uint8_t* tag, int64_t n
   const int T = (int)(M.ts / BLK);
   const int64_t NT = M.NT;
   const int64_t nb_off = NT * (NT - 1) / 2 * T * T, nb64 = (NT + nband) * T * T;
+  const int64_t t64 = M.ts / 64, npt = t64 * (t64 + 1) / 2, nlow = NT * (NT + 1) / 2 * npt,
+                ntr = nlow + nband * npt;
+  hipLaunchKernelGGL(k_transpose_tiles_lp, dim3((unsigned)ntr), dim3(256), 0, s, M, npt, nlow, ntr);
   if (nb_off > 0)
     hipLaunchKernelGGL(k_lauum_contract_lp, dim3((unsigned)nb_off), dim3(256), 0, s, M, tag, T, nreal, xs, ys, av, qt,
                        cst, part, nb_off);
-  hipLaunchKernelGGL(k_lauum_f64_lp, dim3((unsigned)nb64), dim3(256), 0, s, M, T, nreal, xs, ys, av, qt, cst,
+  hipLaunchKernelGGL(k_lauum_f64_lp, dim3((unsigned)nb64), dim3(256), 0, s, M, tag, T, nreal, xs, ys, av, qt, cst,
                      part + 3 * nb_off, nb64, li, lj);
   return nb_off + nb64;
 }

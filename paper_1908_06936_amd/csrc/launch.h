@@ -71,9 +71,23 @@ void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, co
 void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, double* rhs, double* a,
                         hipStream_t s);
 // one step of the mixed inverse (FP32 off-diagonal tiles of L^-1, FP32 buffer P)
-void launch_trtri_right_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, int64_t k,
-                           int64_t nreal, hipStream_t s);
-void launch_trtri_rest_lp(const TileMat& M, const double* Xk, float* P, int64_t k, int64_t nreal, hipStream_t s);
+// The FP64 band tiles of the mixed factor: device lists li / lj (tile (li[e],
+// lj[e]), column-major order, pool slot e) and rl (list entries in row-major
+// order), with host arrays of the first entry of each tile column (cfirst,
+// into li / lj) and of each tile row (rfirst, into rl), NT + 1 each.
+struct BandLists {
+  const int32_t* li;
+  const int32_t* lj;
+  const int32_t* rl;
+  const int64_t* cfirst;
+  const int64_t* rfirst;
+};
+// step k of the mixed inverse (P: FP32 staging, Q: FP64 staging of the band
+// tiles, each (NT - 1) ts^2 elements)
+void launch_trtri_right_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, double* Q,
+                           const BandLists& bl, int64_t k, int64_t nreal, hipStream_t s);
+void launch_trtri_rest_lp(const TileMat& M, const uint8_t* tag, const double* Xk, float* P, double* Q,
+                          const BandLists& bl, int64_t k, int64_t nreal, hipStream_t s);
 // mixed fused LAUUM + contraction; returns the number of partial triples
 int64_t launch_lauum_contract_lp(const TileMat& M, const uint8_t* tag, int64_t nreal, const double* xs,
                                  const double* ys, const double* av, const double* qt, const double* cst,

@@ -310,9 +310,10 @@ def test_mixed_grad_exact_when_off_diagonal_is_zero(orc, exa):
 
 @pytest.mark.parametrize("beta,nu", [(0.03, 0.5), (0.1, 0.5), (0.1, 1.0)])
 def test_mixed_score_record(orc, exa, beta, nu):
-    # the score's error is stated per result, not bounded by the claim on l:
     # the a^T dSigma a term uses the refined a, the trace term the mixed
-    # inverse factor; printed here (default map and the FP32-only record)
+    # inverse factor (FP64 on the factor's FP64 band, FP32 elsewhere).  The
+    # default map claims 1e-8 of max |g| against the oracle here (observed
+    # <= 4e-10); the FP32-only map is printed as a record.
     x, y = inputgen.jittered_grid(40, seed=2)
     th = [1.0, beta, nu]
     z = orc.simulate(x, y, th, inputgen.normals(x.size, seed=2))
@@ -326,6 +327,8 @@ def test_mixed_score_record(orc, exa, beta, nu):
         print(f"mixed score beta={beta} nu={nu} {label}: l rel {rel(lmx, lref):.2e}, score err / max|g| = "
               f"{err / np.abs(gref).max()}, per component {err / np.abs(gref)}")
         assert np.all(np.isfinite(gmx))
+        if label == "default map":
+            assert np.all(err <= 1e-8 * np.abs(gref).max())
 
 
 def test_mixed_lbfgsb_mle_matches_fp64(orc, exa):
