@@ -454,8 +454,8 @@ def profile_mixed(args) -> int:
     the m x m jittered grid (--big-n-side, default 200: n = 40,000), theta =
     (1, --mle-beta, --profile-nu), or with --profile-field uniform on the
     headline workload (n = m^2 uniform points, theta = (1, 0.1, 1.0)), tile
-    768, after one warm-up; one JSON line with the per-phase times and tile
-    fractions."""
+    768, after one warm-up, with the BF16 targets on --profile-bf16-block
+    blocks; one JSON line with the per-phase times and tile fractions."""
     import torch
 
     import inputgen
@@ -473,6 +473,7 @@ def profile_mixed(args) -> int:
     X, Y = torch.as_tensor(x, device=dev), torch.as_tensor(y, device=dev)
     E = torch.as_tensor(inputgen.normals(x.size, seed=0), device=dev)
     ctx = exa.Context(ts=768)
+    ctx.set_mixed_bf16_block(args.profile_bf16_block)
     Z = ctx.simulate(X, Y, th, E)
     prec = args.profile_precision
     ctx.loglik_grad(X, Y, Z, th, prec)
@@ -533,6 +534,8 @@ def main() -> int:
     ap.add_argument("--profile-nu", type=float, default=0.5)
     ap.add_argument("--profile-precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--profile-field", default="grid", choices=["grid", "uniform"])
+    ap.add_argument("--profile-bf16-block", type=int, default=256, choices=[128, 256],
+                    help="output block edge of the BF16 targets' update in --profile-mixed")
     args = ap.parse_args()
 
     if args.copy_calibration:

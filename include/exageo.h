@@ -159,6 +159,14 @@ exageo_status exageo_set_mixed_fp64_band(exageo_ctx *ctx, double fp64_band_facto
  * y = L^-1 z).  EINVAL if steps < 0 or > 8. */
 exageo_status exageo_set_mixed_refinement(exageo_ctx *ctx, int steps);
 
+/* Output block edge of the BF16 targets' update in EXAGEO_MIXED (paper
+ * Section 2.1, the half-precision tiles): 256 (default; used when the tile
+ * size is a multiple of 256, one 512-thread workgroup per 256 x 256 block) or
+ * 128 (the 128 x 128 blocks of the FP32 targets' kernel).  Both form every
+ * product and sum in the same order, so l and its score are the same bits;
+ * the wide block reads half the operand bytes per flop.  EINVAL otherwise. */
+exageo_status exageo_set_mixed_bf16_block(exageo_ctx *ctx, int edge);
+
 /* Distance between locations (paper Section 3, the dmetric argument):
  * EXAGEO_EUCLIDEAN (default) on (x, y), or EXAGEO_GREAT_CIRCLE: x = longitude
  * and y = latitude in degrees, distance along the sphere of radius 6371 (km,

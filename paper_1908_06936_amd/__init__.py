@@ -156,6 +156,10 @@ class Context:
         """FP64 refinement steps of Sigma^-1 z through the mixed factor."""
         self._check(self._lib.exageo_set_mixed_refinement(self._h, int(steps)), "set_mixed_refinement")
 
+    def set_mixed_bf16_block(self, edge: int = 256):
+        """Output block edge (256 or 128) of the BF16 targets' update."""
+        self._check(self._lib.exageo_set_mixed_bf16_block(self._h, int(edge)), "set_mixed_bf16_block")
+
     def set_distance(self, metric: str):
         """'euclidean' (default) or 'great_circle' (x = longitude, y = latitude
         in degrees, km on a sphere of radius 6371)."""

@@ -30,7 +30,7 @@ class MleStats(ctypes.Structure):
 EXPORTS = [
     "exageo_create", "exageo_destroy", "exageo_set_stream", "exageo_workspace_bytes", "exageo_set_workspace",
     "exageo_set_mixed_policy", "exageo_set_mixed_fp64_band", "exageo_set_mixed_correlation",
-    "exageo_set_mixed_refinement", "exageo_set_dst_band", "exageo_set_distance", "exageo_set_nugget", "exageo_set_verbose", "exageo_last_error",
+    "exageo_set_mixed_refinement", "exageo_set_mixed_bf16_block", "exageo_set_dst_band", "exageo_set_distance", "exageo_set_nugget", "exageo_set_verbose", "exageo_last_error",
     "exageo_matern_cov",
     "exageo_simulate", "exageo_loglik",
     "exageo_loglik_grad", "exageo_loglik_grad_noalloc", "exageo_mle", "exageo_predict", "exageo_fisher", "exageo_get_timings", "exageo_set_profiling",
@@ -68,6 +68,8 @@ def load():
     lib.exageo_set_mixed_correlation.argtypes = [p, d, d]
     lib.exageo_set_mixed_refinement.restype = st
     lib.exageo_set_mixed_refinement.argtypes = [p, i32]
+    lib.exageo_set_mixed_bf16_block.restype = st
+    lib.exageo_set_mixed_bf16_block.argtypes = [p, i32]
     lib.exageo_set_dst_band.restype = st
     lib.exageo_set_dst_band.argtypes = [p, i64]
     lib.exageo_set_distance.restype = st

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libexageo.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["k_matern.hip", "k_small.hip", "k_gemm.hip", "k_mixed.hip", "k_predict.hip", "k_fisher.hip", "noalloc.hip", "exageo.cpp", "optim.cpp"]
+SOURCES = ["k_matern.hip", "k_small.hip", "k_gemm.hip", "k_mixed.hip", "k_bf16.hip", "k_predict.hip", "k_fisher.hip", "noalloc.hip", "exageo.cpp", "optim.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -29,7 +29,7 @@ struct Plan {
   size_t off_diag = 0, off_offt = 0, off_xd = 0, off_dinv = 0, off_ld = 0, off_xs = 0, off_ys = 0, off_zs = 0, off_yv = 0,
          off_av = 0, off_perm = 0, off_keys = 0, off_box = 0, off_qt = 0, off_cst = 0, off_part = 0, off_out = 0,
          off_info = 0, off_tmp = 0, off_y = 0, off_alpha = 0, off_ptmp = 0, off_pbuf = 0, off_p32 = 0, off_pbt = 0, off_tag = 0,
-         off_tbox = 0, off_pool = 0, off_pidx = 0, off_bli = 0, off_blj = 0, off_brl = 0, off_corr = 0, off_rtry = 0,
+         off_tbox = 0, off_pool = 0, off_pidx = 0, off_bli = 0, off_blj = 0, off_brl = 0, off_b16i = 0, off_b16j = 0, off_corr = 0, off_rtry = 0,
          off_rnrm = 0, off_fb = 0, off_fstrip = 0, off_fpart = 0, off_fout = 0, off_dmin = 0;
   size_t ptmp_doubles = 0;  // FP64 staging of the inverse (also the kriging blocks)
   int nfisher = 0;          // derivative matrices held for the Fisher information (0, 2 or 3)
@@ -83,6 +83,8 @@ Plan make_plan(int64_t n, int64_t ts, int want_grad, int precision = EXAGEO_FP64
     p.off_bli = take((size_t)std::max<int64_t>(1, p.pool_cap) * 4);
     p.off_blj = take((size_t)std::max<int64_t>(1, p.pool_cap) * 4);
     p.off_brl = take((size_t)std::max<int64_t>(1, p.pool_cap) * 4);  // band list entries by tile rows
+    p.off_b16i = take(noff * 4);  // BF16 tiles, column-major list
+    p.off_b16j = take(noff * 4);
   }
   p.off_xd = take((size_t)p.NT * tt * 8);
   // FP64 inverse: FP64 staging buffer (the mixed inverse stages in the FP32 panel copy)
@@ -173,6 +175,9 @@ struct exageo_ctx {
   std::vector<int64_t> bfirst;
   // the same list by tile rows: rl[r] = list entry, rfirst[i] = first r of row i
   std::vector<int64_t> brfirst;
+  // BF16 tiles in column-major order and the first entry of each tile column
+  std::vector<int64_t> b16first;
+  int bf16_block = 256;  // output block edge of the BF16 update (256 when ts allows, else 128)
   // side stream (default priority) for the lookahead panel, and its events
   hipStream_t side = nullptr;
   hipEvent_t ev_col = nullptr, ev_panel = nullptr;
@@ -293,7 +298,7 @@ exageo_status prepare_locations(exageo_ctx* c, const Plan& p, const double* x, c
 // off-diagonal tile is FP32.  Returns the BF16 and FP64 fractions.
 exageo_status upload_tags(exageo_ctx* c, const Plan& p, const double theta[3], double* frac_bf16, double* frac_fp64) {
   const size_t noff = (size_t)std::max<int64_t>(1, p.NT * (p.NT - 1) / 2);
-  const size_t words = noff + 3 * (size_t)std::max<int64_t>(1, p.pool_cap);
+  const size_t words = 3 * noff + 3 * (size_t)std::max<int64_t>(1, p.pool_cap);
   if (c->htag_bytes < noff) {
     if (c->htag) HIPCHK(c, hipHostFree(c->htag));
     c->htag = nullptr;
@@ -395,12 +400,31 @@ exageo_status upload_tags(exageo_ctx* c, const Plan& p, const double theta[3], d
     c->htag[0] = exg::TAG_F32;
     pidx[0] = -1;
   }
+  // BF16 list (column-major tile order)
+  int32_t* b16i = rl + std::max<int64_t>(1, p.pool_cap);
+  int32_t* b16j = b16i + noff;
+  c->b16first.assign((size_t)p.NT + 1, 0);
+  int64_t n16 = 0;
+  for (int64_t j = 0; j < p.NT; ++j) {
+    c->b16first[(size_t)j] = n16;
+    for (int64_t i = j + 1; i < p.NT; ++i)
+      if (c->htag[exg::off_index(i, j, p.NT)] == exg::TAG_BF16) {
+        b16i[n16] = (int32_t)i;
+        b16j[n16] = (int32_t)j;
+        ++n16;
+      }
+  }
+  c->b16first[(size_t)p.NT] = n16;
   HIPCHK(c, hipMemcpyAsync(at<uint8_t>(c, p.off_tag), c->htag, noff, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_pidx), pidx, noff * 4, hipMemcpyHostToDevice, c->stream));
   if (nb64 > 0) {
     HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_bli), li, (size_t)nb64 * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_blj), lj, (size_t)nb64 * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_brl), rl, (size_t)nb64 * 4, hipMemcpyHostToDevice, c->stream));
+  }
+  if (n16 > 0) {
+    HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_b16i), b16i, (size_t)n16 * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(at<int32_t>(c, p.off_b16j), b16j, (size_t)n16 * 4, hipMemcpyHostToDevice, c->stream));
   }
   *frac_bf16 = ntot ? (double)nbf / (double)ntot : 0.0;
   *frac_fp64 = ntot ? (double)nb64 / (double)ntot : 0.0;
@@ -461,6 +485,10 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
   const bool any_bf16 = p.mixed && c->timings[11] > 0.0;
   const int32_t* bli = p.mixed ? at<int32_t>(c, p.off_bli) : nullptr;
   const int32_t* blj = p.mixed ? at<int32_t>(c, p.off_blj) : nullptr;
+  // BF16 targets on 256 x 256 blocks when the tile edge allows
+  const bool wide16 = any_bf16 && c->bf16_block == 256 && p.ts % 256 == 0;
+  const int32_t* b16i = p.mixed ? at<int32_t>(c, p.off_b16i) : nullptr;
+  const int32_t* b16j = p.mixed ? at<int32_t>(c, p.off_b16j) : nullptr;
   const size_t phalf = (size_t)std::max<int64_t>(1, p.NT - 1) * tt;
   auto panel = [&](int64_t k, hipStream_t s) -> double* {
     double* below = nullptr;
@@ -492,7 +520,11 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
     if (p.mixed) {
       const int64_t e0 = c->bfirst[k + 1], e1 = c->bfirst[k + 2];
       exg::launch_band_update(M, below, k, p.n, bli, blj, e0, e1 - e0, S);
-      exg::launch_update_lp(M, tag, p32, pbt, k, p.n, exg::UPD_FIRST_COLUMN, S);
+      exg::launch_update_lp(M, tag, p32, pbt, k, p.n, exg::UPD_FIRST_COLUMN, wide16, S);
+      if (wide16) {
+        const int64_t f0 = c->b16first[k + 1], f1 = c->b16first[k + 2];
+        exg::launch_update_bf16(M, b16i, b16j, f0, f1 - f0, pbt, k, p.n, S);
+      }
     }
     HIPCHK(c, hipEventRecord(c->ev_col, S));
     HIPCHK(c, hipStreamWaitEvent(S2, c->ev_col, 0));
@@ -502,7 +534,11 @@ exageo_status factorize(exageo_ctx* c, const Plan& p, const double theta[3]) {
     if (p.mixed) {
       const int64_t e0 = c->bfirst[k + 2], e1 = c->bfirst[p.NT];
       exg::launch_band_update(M, below, k, p.n, bli, blj, e0, e1 - e0, S);
-      exg::launch_update_lp(M, tag, p32, pbt, k, p.n, exg::UPD_REST, S);
+      exg::launch_update_lp(M, tag, p32, pbt, k, p.n, exg::UPD_REST, wide16, S);
+      if (wide16) {
+        const int64_t f0 = c->b16first[k + 2], f1 = c->b16first[p.NT];
+        exg::launch_update_bf16(M, b16i, b16j, f0, f1 - f0, pbt, k, p.n, S);
+      }
     }
     if (slot + 1 < c->nev_created) rec(c, slot + 1);
     HIPCHK(c, hipStreamWaitEvent(S, c->ev_panel, 0));
@@ -840,6 +876,12 @@ exageo_status exageo_set_mixed_correlation(exageo_ctx* c, double fp64_at_or_abov
 exageo_status exageo_set_mixed_refinement(exageo_ctx* c, int steps) {
   if (!c || steps < 0 || steps > 8) return EXAGEO_EINVAL;
   c->refine = steps;
+  return EXAGEO_OK;
+}
+
+exageo_status exageo_set_mixed_bf16_block(exageo_ctx* c, int edge) {
+  if (!c || (edge != 128 && edge != 256)) return EXAGEO_EINVAL;
+  c->bf16_block = edge;
   return EXAGEO_OK;
 }
 

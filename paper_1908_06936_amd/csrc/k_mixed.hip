@@ -242,7 +242,8 @@ __global__ __launch_bounds__(256) void k_panel_bf16t(const double* __restrict__ 
 __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* __restrict__ tag,
                                                       const float* __restrict__ p32,
                                                       const uint16_t* __restrict__ pbt, int T, int64_t k,
-                                                      int64_t nreal, int64_t nb, int mode, int64_t off) {
+                                                      int64_t nreal, int64_t nb, int mode, int64_t off,
+                                                      int skip_bf16) {
   constexpr int SMB = G32_LDS * 4 > GB_LDS_BYTES ? G32_LDS * 4 : GB_LDS_BYTES;
   __shared__ __attribute__((aligned(16))) char smraw[SMB];
   const int64_t ts = M.ts, tt = ts * ts;
@@ -258,6 +259,7 @@ __global__ __launch_bounds__(256, 2) void k_update_lp(TileMat M, const uint8_t* 
   const int64_t ic = off_index(i, j, M.NT);
   const int tg = tag[ic];
   if (tg == TAG_F64) return;  // FP64 band target: updated by the FP64 kernel
+  if (tg == TAG_BF16 && skip_bf16) return;  // on the 256 x 256 BF16 kernel
   float* C = (float*)M.off + ic * tt;
   if (tg == TAG_BF16 && pbt) {
     v4f acc[4][4];
@@ -860,7 +862,7 @@ void launch_panel_bf16t(const TileMat& M, int64_t k, const double* pbuf, uint16_
 }
 
 void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, const uint16_t* pbt, int64_t k,
-                      int64_t nreal, int part, hipStream_t s) {
+                      int64_t nreal, int part, bool skip_bf16, hipStream_t s) {
   const int T = (int)(M.ts / BLK);
   const int64_t m = M.NT - k - 2;  // strictly-lower pairs among the m + 1 trailing tiles
   if (m <= 0) return;
@@ -874,7 +876,7 @@ void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, co
   if (npairs <= 0) return;
   const int64_t nblk = npairs * T * T;
   hipLaunchKernelGGL(k_update_lp, dim3((unsigned)nblk), dim3(256), 0, s, M, tag, p32, pbt, T, k, nreal, nblk, mode,
-                     off);
+                     off, (int)skip_bf16);
 }
 
 void launch_trsv_fwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, int64_t nreal, double* rhs,

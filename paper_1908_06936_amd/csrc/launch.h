@@ -66,8 +66,14 @@ void launch_panel_scatter(const TileMat& M, int64_t k, const uint8_t* tag, const
                           hipStream_t s);
 // BF16 copy of the FP64 panel of step k, each tile transposed (k contiguous)
 void launch_panel_bf16t(const TileMat& M, int64_t k, const double* pbuf, uint16_t* pbt, hipStream_t s);
+// skip_bf16: BF16 targets are left to launch_update_bf16
 void launch_update_lp(const TileMat& M, const uint8_t* tag, const float* p32, const uint16_t* pbt, int64_t k,
-                      int64_t nreal, int part, hipStream_t s);
+                      int64_t nreal, int part, bool skip_bf16, hipStream_t s);
+// step k of the mixed update for the BF16 targets (li[e], lj[e]), e0 <= e <
+// e0 + count, on 256 x 256 blocks (ts a multiple of 256); pbt: the BF16 panel
+// copy of step k (tiles transposed)
+void launch_update_bf16(const TileMat& M, const int32_t* li, const int32_t* lj, int64_t e0, int64_t count,
+                        const uint16_t* pbt, int64_t k, int64_t nreal, hipStream_t s);
 void launch_trsv_bwd_lp(const TileMat& M, const uint8_t* tag, const double* Xd, double* rhs, double* a,
                         hipStream_t s);
 // one step of the mixed inverse (FP32 off-diagonal tiles of L^-1, FP32 buffer P)

@@ -94,6 +94,7 @@ def test_entry_points_reject_bad_arguments_before_any_launch(lib):
     assert lib.exageo_loglik(None, 10, None, None, None, theta, 0, ctypes.byref(ll), None) == EINVAL
     assert lib.exageo_set_mixed_policy(None, 3.0) == EINVAL
     assert lib.exageo_set_mixed_fp64_band(None, 1.0) == EINVAL
+    assert lib.exageo_set_mixed_bf16_block(None, 256) == EINVAL
     assert lib.exageo_last_error(None) == b"null context"
 
 
