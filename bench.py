@@ -499,6 +499,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=40000)
     ap.add_argument("--ts", type=int, default=768)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip the n = 10,000 and n = 400 studies (profiles of the n = 40,000 kernels alone)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the l-only and FP64-vs-mixed sections (profiling runs of the headline step)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -654,43 +656,44 @@ def main() -> int:
         "loglik": lls[-1][0],
         "grad": lls[-1][1],
     }
-    # the two small studies of the workload list: n = 10,000 (100 x 100
-    # jittered grid, tile 512, six (beta, nu)), one l each; n = 400 (20 x 20
-    # jittered grid, theta = (1, 0.1, 0.5)), one l and the derivative-free MLE
-    # from the lower bound (0.001, 0.001, 0.001) with tolerance 1e-4
-    x2, y2 = inputgen.jittered_grid(100, seed=0)
-    X2, Y2 = torch.as_tensor(x2, device=dev), torch.as_tensor(y2, device=dev)
-    E2 = torch.as_tensor(inputgen.normals(x2.size, seed=0), device=dev)
-    ctx2 = exa.Context(ts=512, device=0)
-    c2 = {}
-    for nu in (0.5, 1.0):
-        for beta in (0.03, 0.1, 0.3):
-            th2 = [1.0, beta, nu]
-            Z2 = ctx2.simulate(X2, Y2, th2, E2)
-            ctx2.loglik(X2, Y2, Z2, th2)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            l2 = ctx2.loglik(X2, Y2, Z2, th2)
-            torch.cuda.synchronize()
-            c2[f"beta={beta},nu={nu}"] = {"loglik": l2, "ms": 1e3 * (time.perf_counter() - t1)}
-    result["n10000_grid_ts512_one_loglik"] = c2
-    x1, y1 = inputgen.jittered_grid(20, seed=0)
-    X1, Y1 = torch.as_tensor(x1, device=dev), torch.as_tensor(y1, device=dev)
-    E1 = torch.as_tensor(inputgen.normals(x1.size, seed=0), device=dev)
-    th1 = [1.0, 0.1, 0.5]
-    Z1 = ctx2.simulate(X1, Y1, th1, E1)
-    ctx2.loglik(X1, Y1, Z1, th1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    l1 = ctx2.loglik(X1, Y1, Z1, th1)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    th1_hat, l1_hat, st1 = ctx2.mle(X1, Y1, Z1, [0.001] * 3, [5.0] * 3, tol=1e-4, method="dfo")
-    result["n400_grid"] = {"loglik": l1, "loglik_ms": 1e3 * (t2 - t1), "dfo_theta_hat": th1_hat,
-                           "dfo_loglik": l1_hat, "dfo_wall_s": st1["total_s"], "dfo_evals": st1["n_evals"],
-                           "dfo_per_eval_ms": 1e3 * st1["per_eval_s"], "dfo_status": st1["status"]}
-    ctx2.close()
-    print("[bench] n = 10,000 and n = 400 studies done", file=sys.stderr, flush=True)
+    if not args.no_studies:
+        # the two small studies of the workload list: n = 10,000 (100 x 100
+        # jittered grid, tile 512, six (beta, nu)), one l each; n = 400 (20 x 20
+        # jittered grid, theta = (1, 0.1, 0.5)), one l and the derivative-free MLE
+        # from the lower bound (0.001, 0.001, 0.001) with tolerance 1e-4
+        x2, y2 = inputgen.jittered_grid(100, seed=0)
+        X2, Y2 = torch.as_tensor(x2, device=dev), torch.as_tensor(y2, device=dev)
+        E2 = torch.as_tensor(inputgen.normals(x2.size, seed=0), device=dev)
+        ctx2 = exa.Context(ts=512, device=0)
+        c2 = {}
+        for nu in (0.5, 1.0):
+            for beta in (0.03, 0.1, 0.3):
+                th2 = [1.0, beta, nu]
+                Z2 = ctx2.simulate(X2, Y2, th2, E2)
+                ctx2.loglik(X2, Y2, Z2, th2)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                l2 = ctx2.loglik(X2, Y2, Z2, th2)
+                torch.cuda.synchronize()
+                c2[f"beta={beta},nu={nu}"] = {"loglik": l2, "ms": 1e3 * (time.perf_counter() - t1)}
+        result["n10000_grid_ts512_one_loglik"] = c2
+        x1, y1 = inputgen.jittered_grid(20, seed=0)
+        X1, Y1 = torch.as_tensor(x1, device=dev), torch.as_tensor(y1, device=dev)
+        E1 = torch.as_tensor(inputgen.normals(x1.size, seed=0), device=dev)
+        th1 = [1.0, 0.1, 0.5]
+        Z1 = ctx2.simulate(X1, Y1, th1, E1)
+        ctx2.loglik(X1, Y1, Z1, th1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        l1 = ctx2.loglik(X1, Y1, Z1, th1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        th1_hat, l1_hat, st1 = ctx2.mle(X1, Y1, Z1, [0.001] * 3, [5.0] * 3, tol=1e-4, method="dfo")
+        result["n400_grid"] = {"loglik": l1, "loglik_ms": 1e3 * (t2 - t1), "dfo_theta_hat": th1_hat,
+                               "dfo_loglik": l1_hat, "dfo_wall_s": st1["total_s"], "dfo_evals": st1["n_evals"],
+                               "dfo_per_eval_ms": 1e3 * st1["per_eval_s"], "dfo_status": st1["status"]}
+        ctx2.close()
+        print("[bench] n = 10,000 and n = 400 studies done", file=sys.stderr, flush=True)
     # kriging at 1,000 new points from the same data (factorisation included)
     xq, yq = inputgen.uniform(1000, seed=5)
     Xq, Yq = torch.as_tensor(xq, device=dev), torch.as_tensor(yq, device=dev)

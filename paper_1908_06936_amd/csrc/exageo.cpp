@@ -1284,10 +1284,12 @@ exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const dou
     c->timings[0] = ev_ms(c, 0, 5);
     c->timings[7] = ev_ms(c, 4, 5);
     // MFMA flops of the two products per parameter over the R real 128-blocks:
-    // X G and M X^T over the lower block pairs (g, h), h <= g, each with a
-    // range of (g + 1) or (h + 1) 128-columns
+    // X G over the lower block pairs (g, h), h <= g, each over g + 1
+    // 128-columns (sum_g (g + 1)^2 = R (R + 1) (2R + 1) / 6 block products),
+    // and M X^T over the same pairs with h + 1 (sum = R (R + 1) (R + 2) / 6);
+    // together R (R + 1)^2 / 2
     const double R = (double)((p.n + BLKH - 1) / BLKH), b3 = 2.0 * BLKH * BLKH * BLKH;
-    c->timings[18] = (nug ? 3.0 : 2.0) * b3 * 2.0 * (R * (R + 1.0) * (R + 2.0) / 6.0);
+    c->timings[18] = (nug ? 3.0 : 2.0) * b3 * (R * (R + 1.0) * (R + 1.0) / 2.0);
   }
   return EXAGEO_OK;
 }
