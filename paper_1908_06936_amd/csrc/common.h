@@ -234,73 +234,6 @@ __device__ __forceinline__ void gemm_core(AP aptr, int64_t lda, BP bptr, int64_t
   }
 }
 
-// The same block product for operands read along their contiguous row index
-// (AKC = BKC = false) with the global loads going straight into LDS
-// (global_load_lds_dwordx4: lane l of a wave writes its 16 bytes at the
-// instruction's LDS base + 16 l, so one instruction fills one 128-double k
-// row of the padded layout).  No registers hold a stage in flight, which
-// leaves room to read the next 4-deep group of operand fragments from LDS
-// while the current group's 16 MFMAs run.  Two LDS buffers: stage st + 1 is
-// loaded while stage st is multiplied; one barrier per stage.  Same results,
-// bit for bit, as gemm_core<false, false> (same products, same order).
-__device__ __forceinline__ void dl_row(const double* g, double* l) {
-  __builtin_amdgcn_global_load_lds((const void*)g, (void __attribute__((address_space(3)))*)l, 16, 0, 0);
-}
-
-template <class AP, class BP>
-__device__ __forceinline__ void gemm_core_dl(AP aptr, int64_t lda, BP bptr, int64_t ldb, int K, v4d (&acc)[4][4],
-                                             double* sm) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  double* sA = sm;
-  double* sB = sm + 2 * BK * LDP;
-  // wave w fills k rows w, w + 4, w + 8, w + 12 of both operands
-  auto load_stage = [&](int k0, int buf) {
-    const double* A = aptr(k0);
-    const double* B = bptr(k0);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = w + 4 * s;
-      dl_row(A + 2 * lane + (int64_t)kk * lda, sA + buf * BK * LDP + kk * LDP);
-      dl_row(B + 2 * lane + (int64_t)kk * ldb, sB + buf * BK * LDP + kk * LDP);
-    }
-  };
-  auto frag = [&](int buf, int kk, double (&af)[4], double (&bf)[4]) {
-    const int ko = buf * BK * LDP + (kk + (lane >> 4)) * LDP + (lane & 15);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) af[i] = sA[ko + wr * 64 + 16 * i];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) bf[j] = sB[ko + wc * 64 + 16 * j];
-  };
-  auto mma = [&](const double (&af)[4], const double (&bf)[4]) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(bf[j], af[i], acc[i][j]);
-  };
-  const int nst = K / BK;
-  load_stage(0, 0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int buf = st & 1;
-    if (st + 1 < nst) load_stage((st + 1) * BK, buf ^ 1);
-    double a0[4], b0[4], a1[4], b1[4];
-    frag(buf, 0, a0, b0);
-    frag(buf, 4, a1, b1);
-    mma(a0, b0);
-    frag(buf, 8, a0, b0);
-    mma(a1, b1);
-    frag(buf, 12, a1, b1);
-    mma(a0, b0);
-    mma(a1, b1);
-    // keep the wait below the MFMAs: the loads of stage st + 1 land meanwhile
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's rows of stage st + 1 are in LDS
-    __syncthreads();                // every wave's, and nobody reads buffer buf any more
-  }
-}
-
 // gemm_core over one contiguous operand pair:
 //   Aop(m, k) = A[m + k lda] (AKC = false) or A[k + m lda] (AKC = true), same for B.
 template <bool AKC, bool BKC>
@@ -315,20 +248,14 @@ __device__ __forceinline__ void gemm_blk(const double* __restrict__ A, int64_t l
 // each XCD with its own L2.  xcd_block maps the dispatch index to a logical
 // block so that XCD x runs the contiguous logical range [x nb8, (x + 1) nb8),
 // nb8 = ceil(nb / 8): the blocks resident on one XCD at a time are neighbours
-// in the launch's block order (the 36 blocks of one tile pair share their 6
-// row blocks of each operand) and reuse each other's operand reads in that
-// XCD's L2.  The grid must have 8 nb8 workgroups; -1 for the spare ones.
+// in the launch's block order and reuse each other's operand reads in that
+// XCD's L2 (used by the BF16 update, whose blocks are bound by operand reads;
+// the FP64 trailing update ran 3.5% slower with it while it halved the bytes
+// fetched past L2).  The grid must have 8 nb8 workgroups; -1 for the spare ones.
 __device__ __forceinline__ int64_t xcd_block(int64_t nb) {
   const int64_t nb8 = (nb + 7) / 8;
   const int64_t b = (int64_t)(blockIdx.x % 8) * nb8 + blockIdx.x / 8;
   return b < nb ? b : -1;
-}
-
-// gemm_core_dl over one contiguous operand pair (both m / n contiguous)
-__device__ __forceinline__ void gemm_blk_dl(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
-                                            int64_t ldb, int K, v4d (&acc)[4][4], double* sm) {
-  gemm_core_dl([=](int k0) { return A + (int64_t)k0 * lda; }, lda, [=](int k0) { return B + (int64_t)k0 * ldb; }, ldb,
-               K, acc, sm);
 }
 
 __device__ __forceinline__ void acc_zero(v4d (&acc)[4][4]) {

@@ -36,8 +36,8 @@ __global__ __launch_bounds__(256, 2) void k_chol_update(TileMat M, const double*
                                                         const int32_t* __restrict__ lj) {
   __shared__ double sm[GEMM_LDS];
   const int64_t ts = M.ts;
-  const int64_t b = xcd_block(nb);
-  if (b < 0) return;
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
   const int64_t p = b / (T * T);
   const int sub = (int)(b % (T * T));
   const int u = sub / T, v = sub % T;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_update(TileMat M, const double*
               (int64_t)v * BLK * ts;
   v4d acc[4][4];
   acc_zero(acc);
-  gemm_blk_dl(A, ts, B, ts, (int)ts, acc, sm);
+  gemm_blk<false, false>(A, ts, B, ts, (int)ts, acc, sm);
   acc_store(C, ts, acc, -1.0, true);
 }
 
@@ -326,7 +326,7 @@ void launch_chol_update(const TileMat& M, const double* below, int64_t k, int64_
   }
   if (npairs <= 0) return;
   const int64_t nblk = npairs * T * T;
-  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)((nblk + 7) / 8 * 8)), dim3(256), 0, s, M, below, T, k, nreal, nblk,
+  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, M, below, T, k, nreal, nblk,
                      mode, off, (const int32_t*)nullptr, (const int32_t*)nullptr);
 }
 
@@ -335,7 +335,7 @@ void launch_band_update(const TileMat& M, const double* below, int64_t k, int64_
   if (count <= 0) return;
   const int T = (int)(M.ts / BLK);
   const int64_t nblk = count * T * T;
-  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)((nblk + 7) / 8 * 8)), dim3(256), 0, s, M, below, T, k, nreal, nblk,
+  hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nblk), dim3(256), 0, s, M, below, T, k, nreal, nblk,
                      (int)PAIRS_LIST, e0, li, lj);
 }
 
