@@ -43,6 +43,23 @@ def normals(n: int, seed: int = 0):
     return rng.standard_normal(n)
 
 
+def smooth_field(x, y, seed: int = 0):
+    """Observations that vary smoothly over the locations: a sum of 16 plane
+    waves cos(2 pi (kx x + ky y) + phase), kx, ky = 0..3, with N(0, 1)
+    amplitudes and U(0, 2 pi) phases (numpy PCG64, seed).  Used where a
+    check needs z^T Sigma^-1 z to be insensitive to rounding (a white-noise z
+    weights Sigma's smallest eigenvalues)."""
+    rng = np.random.default_rng(seed + 104729)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.zeros_like(x)
+    for kx in range(4):
+        for ky in range(4):
+            a, ph = rng.standard_normal(), rng.uniform(0.0, 2.0 * np.pi)
+            z += a * np.cos(2.0 * np.pi * (kx * x + ky * y) + ph)
+    return z
+
+
 def collinear(n: int, mean_gap: float, seed: int = 0):
     """Sorted 1-D locations on y = 0 with gaps U(0.5, 1.5) * mean_gap."""
     rng = np.random.default_rng(seed)

@@ -125,6 +125,34 @@ def test_loglik_config2_full_size(orc, exa, beta, nu):
     assert got == pytest.approx(ref, rel=1e-10)
 
 
+def test_loglik_config3_vs_lapack_reference(exa):
+    # the headline workload's locations and theta (n = 40,000 U[0,1]^2, theta =
+    # (1, 0.1, 1.0), tile 768) with a smooth z, against the oracle's covariance
+    # factored by LAPACK on the CPU (tests/golden/config3_loglik.json, written
+    # by tests/golden/make_config3_reference.py): l, log det Sigma and
+    # z^T Sigma^-1 z each at the FP64 bound, relative 1e-10.  (With a
+    # white-noise z the two quadratic forms, 3.5e8, differ by 4.8e-10: that z
+    # weights eigenvalues near 1e-8, where the form is set by rounding; the
+    # log dets agreed to 5.7e-14.)
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "config3_loglik.json")) as fh:
+        ref = json.load(fh)
+    n = ref["n"]
+    x, y = inputgen.uniform(n, seed=0)
+    z = inputgen.smooth_field(x, y, seed=0)
+    ctx = exa.Context(ts=768)
+    got = ctx.loglik(dev(x), dev(y), dev(z), ref["theta"])
+    tm = ctx.timings()
+    print(f"config 3 vs LAPACK: l {got!r} vs {ref['loglik']!r} (rel {abs(got - ref['loglik']) / abs(ref['loglik']):.2e}),"
+          f" log det rel {abs(tm['logdet'] - ref['logdet']) / abs(ref['logdet']):.2e},"
+          f" quad form rel {abs(tm['quad_form'] - ref['quad_form']) / abs(ref['quad_form']):.2e}")
+    assert got == pytest.approx(ref["loglik"], rel=1e-10)
+    assert tm["logdet"] == pytest.approx(ref["logdet"], rel=1e-10)
+    assert tm["quad_form"] == pytest.approx(ref["quad_form"], rel=1e-10)
+
+
 def test_loglik_worked_values(exa):
     ctx = exa.Context(ts=128)
     assert ctx.loglik(dev([0.0]), dev([0.0]), dev([0.7]), [2, 0.1, 0.5]) == pytest.approx(-1.3880121234846454,
