@@ -8,14 +8,16 @@
 //   1. the column-k tiles below the diagonal are widened into an FP64 panel
 //      buffer, the panel is factored by the FP64 kernels and written back,
 //      rounded to nearest even into each tile's precision and, for the
-//      update, to FP32 in a panel copy;
-//   2. diagonal targets A_jj -= A_jk A_jk^T run on FP64 MFMA from the FP64
-//      panel buffer (k_chol_update with diag_only);
-//   3. off-diagonal targets A_ij -= A_ik A_jk^T run on FP32 MFMA with FP32
-//      accumulation from the FP32 panel copy; BF16 targets are widened
-//      exactly and rounded back to nearest even.
+//      update, to FP32 (and BF16, transposed) in panel copies;
+//   2. diagonal and FP64 band targets A_ij -= A_ik A_jk^T run on FP64 MFMA
+//      from the FP64 panel buffer (k_chol_update);
+//   3. FP32 targets run on FP32 MFMA with FP32 accumulation from the FP32
+//      panel copy (k_update_lp); BF16 targets on BF16 MFMA with FP32
+//      accumulation from the BF16 copy, widened exactly and rounded back to
+//      nearest even (k_update_bf16 in k_bf16.hip, or k_update_lp).
 // The solves read the stored tiles and accumulate in FP64; log det Sigma and
-// z^T Sigma^-1 z are FP64 sums.
+// z^T Sigma^-1 z are FP64 sums.  The inverse factor and the fused LAUUM for
+// the score follow the same precision map (below).
 #include <float.h>
 
 #include "common.h"
