@@ -33,16 +33,21 @@ typedef float fl2 __attribute__((ext_vector_type(2)));
 // store of the FP64 core; FP32 sources are widened (exactly) at the store
 template <typename T>
 struct Pair2;
+// bytes in the global address space (loads through it are global, not flat)
+typedef __attribute__((address_space(1))) const char gbyte;
+
 template <>
 struct Pair2<double> {
   d2 v;
   __device__ __forceinline__ void load(const double* p) { v = *(const d2*)p; }
+  __device__ __forceinline__ void load_g(gbyte* p) { v = *(__attribute__((address_space(1))) const d2*)p; }
   __device__ __forceinline__ d2 get() const { return v; }
 };
 template <>
 struct Pair2<float> {
   fl2 v;
   __device__ __forceinline__ void load(const float* p) { v = *(const fl2*)p; }
+  __device__ __forceinline__ void load_g(gbyte* p) { v = *(__attribute__((address_space(1))) const fl2*)p; }
   __device__ __forceinline__ d2 get() const { return (d2){(double)v.x, (double)v.y}; }
 };
 
@@ -126,6 +131,15 @@ __device__ __forceinline__ v4d mfma64(double x, double y, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
 }
 
+// A pointer that every lane of the workgroup holds, moved to scalar registers
+// (the caller guarantees that it is the same in every lane).
+__device__ __forceinline__ gbyte* uniform_base(const void* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (gbyte*)(((uint64_t)hi << 32) | lo);
+}
+
 // One 128 x 128 block of  sum_k Aop(m, k) Bop(n, k)  accumulated into acc,
 // over a virtual k range [0, K) that may run across several tiles.
 //   aptr(k0) returns the address of Aop(0, k0) for a stage starting at k0;
@@ -139,7 +153,11 @@ __device__ __forceinline__ v4d mfma64(double x, double y, v4d c) {
 // columns n = wc*64 + 16 j + 4 r + (lane >> 4), r = 0..3 (wr = wave >> 1,
 // wc = wave & 1); with this assignment the lanes of one store instruction
 // write 16 consecutive rows of a column-major output.
-template <bool AKC, bool BKC, class AP, class BP>
+// SB = true: each stage's operand addresses are aptr(k0) / bptr(k0), which must
+// then be the same in every lane, held in scalar registers plus one 32-bit byte
+// offset per thread and load (so 127 lda + 15 elements must stay below 4 GiB);
+// this frees about 14 vector registers.  SB = false: 64-bit vector addresses.
+template <bool AKC, bool BKC, bool SB = false, class AP, class BP>
 __device__ __forceinline__ void gemm_core(AP aptr, int64_t lda, BP bptr, int64_t ldb, int K, v4d (&acc)[4][4],
                                           double* sm) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -151,7 +169,26 @@ __device__ __forceinline__ void gemm_core(AP aptr, int64_t lda, BP bptr, int64_t
   // two register sets: the global loads run two stages ahead of the MFMAs
   Pair2<TA> ra0[4], ra1[4];
   Pair2<TB> rb0[4], rb1[4];
+  uint32_t oa[4], ob[4];  // SB: byte offsets of the thread's pairs within a stage
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int idx = t + GEMM_THREADS * s;
+    oa[s] = (uint32_t)(sizeof(TA) * (AKC ? 2 * (idx & 7) + (int64_t)(idx >> 3) * lda
+                                         : 2 * (idx & 63) + (int64_t)(idx >> 6) * lda));
+    ob[s] = (uint32_t)(sizeof(TB) * (BKC ? 2 * (idx & 7) + (int64_t)(idx >> 3) * ldb
+                                         : 2 * (idx & 63) + (int64_t)(idx >> 6) * ldb));
+  }
   auto gload = [&](int k0, Pair2<TA> (&ra)[4], Pair2<TB> (&rb)[4]) {
+    if constexpr (SB) {
+      gbyte* A = uniform_base(aptr(k0));
+      gbyte* B = uniform_base(bptr(k0));
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        ra[s].load_g(A + oa[s]);
+        rb[s].load_g(B + ob[s]);
+      }
+      return;
+    }
     const TA* A = aptr(k0);
     const TB* B = bptr(k0);
 #pragma unroll
@@ -236,12 +273,12 @@ __device__ __forceinline__ void gemm_core(AP aptr, int64_t lda, BP bptr, int64_t
 
 // gemm_core over one contiguous operand pair:
 //   Aop(m, k) = A[m + k lda] (AKC = false) or A[k + m lda] (AKC = true), same for B.
-template <bool AKC, bool BKC>
+template <bool AKC, bool BKC, bool SB = false>
 __device__ __forceinline__ void gemm_blk(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
                                          int64_t ldb, int K, v4d (&acc)[4][4], double* sm) {
   auto ap = [=](int k0) { return AKC ? A + k0 : A + (int64_t)k0 * lda; };
   auto bp = [=](int k0) { return BKC ? B + k0 : B + (int64_t)k0 * ldb; };
-  gemm_core<AKC, BKC>(ap, lda, bp, ldb, K, acc, sm);
+  gemm_core<AKC, BKC, SB>(ap, lda, bp, ldb, K, acc, sm);
 }
 
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b mod 8),

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_update(TileMat M, const double*
               (int64_t)v * BLK * ts;
   v4d acc[4][4];
   acc_zero(acc);
-  gemm_blk<false, false>(A, ts, B, ts, (int)ts, acc, sm);
+  gemm_blk<false, false, true>(A, ts, B, ts, (int)ts, acc, sm);
   acc_store(C, ts, acc, -1.0, true);
 }
 
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256, 2) void k_panel_update(double* __restrict__ Dk
   const double* D = Dk + c * BLK;
   v4d acc[4][4];
   acc_zero(acc);
-  gemm_blk<false, false>(P, ts, D, ts, c * BLK, acc, sm);
+  gemm_blk<false, false, true>(P, ts, D, ts, c * BLK, acc, sm);
   acc_store(P + (int64_t)c * BLK * ts, ts, acc, -1.0, true);
 }
 

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256, 2) void k_trsm_diag(const double* __restrict__
   v4d acc[4][4];
   acc_zero(acc);
   // Aop(m, q) = X[u*128 + m, q], Bop(n, q) = C[q, cb*128 + n]
-  gemm_blk<false, true>(Xk + u * BLK, ts, Ck + cb * BLK * ld, ld, (u + 1) * BLK, acc, sm);
+  gemm_blk<false, true, true>(Xk + u * BLK, ts, Ck + cb * BLK * ld, ld, (u + 1) * BLK, acc, sm);
   acc_store(Vk + u * BLK + cb * BLK * ld, ld, acc, 1.0, false);
 }
 
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256, 2) void k_trsm_update(TileMat M, int64_t k, in
   v4d acc[4][4];
   acc_zero(acc);
   // Aop(m, q) = L_ik[u*128 + m, q], Bop(n, q) = V_k[q, cb*128 + n]
-  gemm_blk<false, true>(tptr(M, i, k) + u * BLK, ts, Vk + cb * BLK * ld, ld, (int)ts, acc, sm);
+  gemm_blk<false, true, true>(tptr(M, i, k) + u * BLK, ts, Vk + cb * BLK * ld, ld, (int)ts, acc, sm);
   acc_store(C + i * ts + u * BLK + cb * BLK * ld, ld, acc, -1.0, true);
 }
 
