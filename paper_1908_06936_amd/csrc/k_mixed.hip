@@ -381,40 +381,54 @@ __device__ __forceinline__ void gemm_core_mix(AP aptr, int64_t lda, BP bptr, int
   double* sB = sm + 2 * BK * LDP;
   // a register set: four element pairs per operand, raw (two doubles, or two
   // floats in the first 8 bytes) and the element type of the stage
+  typedef uint32_t e4 __attribute__((ext_vector_type(4)));
+  typedef uint32_t e2 __attribute__((ext_vector_type(2)));
   struct Set {
-    uint4 a[4], b[4];
+    e4 a[4], b[4];
     bool fa, fb;
   };
   Set r0, r1;
-  auto eoff = [&](bool kc, int idx, int64_t ld) -> int64_t {
-    return kc ? 2 * (idx & 7) + (int64_t)(idx >> 3) * ld : 2 * (idx & 63) + (int64_t)(idx >> 6) * ld;
-  };
+  // element offsets of the thread's pairs within a stage (fixed for the whole
+  // k range); each stage's base address is the same in every lane and is held
+  // in scalar registers, the byte offset is the element offset shifted by the
+  // stage's element size (127 ld + 15 elements must stay below 2^29)
+  uint32_t ea[4], eb[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int idx = t + GEMM_THREADS * s;
+    ea[s] = (uint32_t)(AKC ? 2 * (idx & 7) + (int64_t)(idx >> 3) * lda : 2 * (idx & 63) + (int64_t)(idx >> 6) * lda);
+    eb[s] = (uint32_t)(BKC ? 2 * (idx & 7) + (int64_t)(idx >> 3) * ldb : 2 * (idx & 63) + (int64_t)(idx >> 6) * ldb);
+  }
+  typedef __attribute__((address_space(1))) const e4 g4;
+  typedef __attribute__((address_space(1))) const e2 g2;
   auto gload = [&](int k0, Set& r) {
     const MixPtr A = aptr(k0), B = bptr(k0);
+    gbyte* pa = uniform_base(A.p);
+    gbyte* pb = uniform_base(B.p);
     r.fa = A.f64;
     r.fb = B.f64;
     if (A.f64) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) r.a[s] = *(const uint4*)((const double*)A.p + eoff(AKC, t + GEMM_THREADS * s, lda));
+      for (int s = 0; s < 4; ++s) r.a[s] = *(g4*)(pa + (ea[s] << 3));
     } else {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const uint2 f = *(const uint2*)((const float*)A.p + eoff(AKC, t + GEMM_THREADS * s, lda));
+        const e2 f = *(g2*)(pa + (ea[s] << 2));
         r.a[s].x = f.x, r.a[s].y = f.y;
       }
     }
     if (B.f64) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) r.b[s] = *(const uint4*)((const double*)B.p + eoff(BKC, t + GEMM_THREADS * s, ldb));
+      for (int s = 0; s < 4; ++s) r.b[s] = *(g4*)(pb + (eb[s] << 3));
     } else {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const uint2 f = *(const uint2*)((const float*)B.p + eoff(BKC, t + GEMM_THREADS * s, ldb));
+        const e2 f = *(g2*)(pb + (eb[s] << 2));
         r.b[s].x = f.x, r.b[s].y = f.y;
       }
     }
   };
-  auto widen = [](const uint4& u, bool f64) -> d2 {
+  auto widen = [](const e4& u, bool f64) -> d2 {
     if (f64) return (d2){__hiloint2double((int)u.y, (int)u.x), __hiloint2double((int)u.w, (int)u.z)};
     return (d2){(double)__uint_as_float(u.x), (double)__uint_as_float(u.y)};
   };
@@ -600,7 +614,7 @@ __global__ __launch_bounds__(256, 2) void k_tri_right_band(TileMat M, const doub
   v4d acc[4][4];
   acc_zero(acc);
   if (i * ts + u * BLK < nreal)
-    gemm_blk<false, true>(band64(M, off_index(i, k, M.NT)) + u * BLK + off, ts, Xk + v * BLK + off, ts,
+    gemm_blk<false, true, true>(band64(M, off_index(i, k, M.NT)) + u * BLK + off, ts, Xk + v * BLK + off, ts,
                           (int)(ts - v * BLK), acc, sm);
   acc_store_pair(Q + o, P + o, ts, acc, -1.0);
 }
@@ -805,7 +819,7 @@ __global__ __launch_bounds__(256, 2) void k_lauum_f64_lp(TileMat M, const uint8_
   const int64_t r0 = (int64_t)u * BLK, c0 = (int64_t)v * BLK;
   const double* XII = M.diag + I * ts * ts;
   const double* XIJ = I == J ? XII : band64(M, off_index(I, J, NT));
-  gemm_blk<false, false>(XII + r0 + r0 * ts, ts, XIJ + c0 + r0 * ts, ts, (int)(ts - r0), acc, sm);
+  gemm_blk<false, false, true>(XII + r0 + r0 * ts, ts, XIJ + c0 + r0 * ts, ts, (int)(ts - r0), acc, sm);
   // K = I + 1 .. NT - 1: each stage lies in one tile K, read in that tile's precision
   if (I + 1 < NT) {
     auto op = [=](int k0, int64_t C, int64_t c) {
