@@ -287,20 +287,24 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract(TileMat M, int T, int
   // One virtual k range over the tiles K = I, ..., NT-1 of tile columns I and
   // J: first rows r0.. of tile row I (X_II is lower triangular, so rows above
   // u*128 of its column block u are zero), then every row of the tiles below.
-  // Transposed tiles: X(K, I)[k, m] sits at k ts + m of tile (K, I).
+  // Transposed tiles: X(K, I)[k, m] sits at k ts + m of tile (K, I).  The
+  // off-diagonal tiles of one tile column are stored one after another, so
+  // row kk of the stack (K, I), K > I, is at kk ts of the stack's first tile
+  // ((kk / ts) ts^2 + (kk % ts) ts = kk ts): no division per stage.
   const int64_t r0 = (int64_t)u * BLK, c0 = (int64_t)v * BLK;
   const int64_t L0 = ts - r0;
+  const double* XdI = M.diag + I * ts * ts;
+  const double* XbI = I + 1 < NT ? (const double*)M.off + off_index(I + 1, I, NT) * ts * ts : XdI;
   auto ap = [=](int k0) -> const double* {
-    if (k0 < L0) return tptr(M, I, I) + r0 + (r0 + k0) * ts;
-    const int64_t kk = k0 - L0, K = I + 1 + kk / ts;
-    return tptr(M, K, I) + r0 + (kk % ts) * ts;
+    return k0 < L0 ? XdI + r0 + (r0 + k0) * ts : XbI + r0 + (int64_t)(k0 - L0) * ts;
   };
+  // I > J: the tiles (I, J), (I + 1, J), ... are one stack as well
+  const double* XJ = I == J ? XbI : tptr(M, I, J);
   auto bp = [=](int k0) -> const double* {
-    if (k0 < L0) return tptr(M, I, J) + c0 + (r0 + k0) * ts;
-    const int64_t kk = k0 - L0, K = I + 1 + kk / ts;
-    return tptr(M, K, J) + c0 + (kk % ts) * ts;
+    if (I > J) return XJ + c0 + (r0 + k0) * ts;
+    return k0 < L0 ? XdI + c0 + (r0 + k0) * ts : XbI + c0 + (int64_t)(k0 - L0) * ts;
   };
-  gemm_core<false, false>(ap, ts, bp, ts, (int)(L0 + (NT - 1 - I) * ts), acc, sm);
+  gemm_core<false, false, true>(ap, ts, bp, ts, (int)(L0 + (NT - 1 - I) * ts), acc, sm);
   contract_block64(acc, I * ts + r0, J * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
 }
 
