@@ -53,6 +53,16 @@ struct Pair2<float> {
 
 __device__ __forceinline__ int64_t tri(int64_t i) { return i * (i + 1) / 2; }
 
+// Quotient a / d for a run of a values against one divisor d >= 2 without a
+// division per call: q(a) is the high half of a m, m = floor(2^32 / d) + 1.
+// With m d = 2^32 + e, 0 < e <= d, a m / 2^32 = a / d + a e / (d 2^32), and the
+// added term stays below 1 / d while a d < 2^32, so q(a) = floor(a / d) exactly.
+struct UDiv {
+  uint32_t m;
+  __device__ __forceinline__ explicit UDiv(int64_t d) : m((uint32_t)(0x100000000ull / (uint64_t)d + 1)) {}
+  __device__ __forceinline__ uint32_t q(uint32_t a) const { return __umulhi(a, m); }
+};
+
 
 
 // The tile matrix: the NT diagonal tiles in one FP64 array, the off-diagonal

@@ -783,8 +783,12 @@ __global__ __launch_bounds__(256, 2) void k_lauum_contract_lp(TileMat M, const u
                                              ts, (int)(ts - r0), acc, sm);
   // K = I + 1 .. NT - 1: every row of the tiles below
   if (I + 1 < NT) {
-    auto ap = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, I) + r0 + (int64_t)(k0 % ts) * ts; };
-    auto bp = [=](int k0) -> const float* { return off32(M, I + 1 + k0 / ts, J) + c0 + (int64_t)(k0 % ts) * ts; };
+    // the slots of one tile column are consecutive: row k0 of the stack of
+    // tiles (I + 1.., C) is at k0 ts of its first tile
+    const float* XI = off32(M, I + 1, I);
+    const float* XJ = off32(M, I + 1, J);
+    auto ap = [=](int k0) -> const float* { return XI + r0 + (int64_t)k0 * ts; };
+    auto bp = [=](int k0) -> const float* { return XJ + c0 + (int64_t)k0 * ts; };
     gemm32<SRC_F32, false, SRC_F32, false>(ap, ts, bp, ts, (int)((NT - 1 - I) * ts), acc, sm);
   }
   contract_block32(acc, I * ts + r0, J * ts + c0, nreal, xs, ys, av, qt, cst, sm, part + 3 * b);
@@ -822,8 +826,10 @@ __global__ __launch_bounds__(256, 2) void k_lauum_f64_lp(TileMat M, const uint8_
   gemm_blk<false, false, true>(XII + r0 + r0 * ts, ts, XIJ + c0 + r0 * ts, ts, (int)(ts - r0), acc, sm);
   // K = I + 1 .. NT - 1: each stage lies in one tile K, read in that tile's precision
   if (I + 1 < NT) {
+    const UDiv dts(ts);  // k0 < npad, npad ts < 2^32
     auto op = [=](int k0, int64_t C, int64_t c) {
-      const int64_t idx = off_index(I + 1 + k0 / ts, C, NT), o = c + (int64_t)(k0 % ts) * ts;
+      const int64_t q = dts.q((uint32_t)k0);
+      const int64_t idx = off_index(I + 1, C, NT) + q, o = c + (k0 - q * ts) * ts;
       if (tag[idx] == TAG_F64) return MixPtr{band64(M, idx) + o, true};
       return MixPtr{(const float*)M.off + idx * ts * ts + o, false};
     };
