@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_BYTES_PER_LAUNCH = (4.9837e6 * 2.0 + 1.0333e6 * 1.0) * 1024
 TRAFFIC_FILES = ("paper_1908_06936_amd/csrc/common.h",)
 TRAFFIC_FUNCTIONS = ("paper_1908_06936_amd/csrc/k_gemm.hip", ("k_chol_update", "launch_chol_update"))
-TRAFFIC_FINGERPRINT = "ab180c5be7ff8f8302f0316c767397f61e6164ca"
+TRAFFIC_FINGERPRINT = "75b22615e038699458018ddce2e921c3b65fd274"
 
 
 def _function_text(src: str, name: str) -> str:
