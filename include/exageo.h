@@ -24,6 +24,10 @@
  *   theta      host array of 3 doubles, (sigma2, beta, nu), all > 0, nu <= 15.
  *   x, y, z    DEVICE pointers to n contiguous doubles (locations and
  *              observations), caller owned, read only, valid for the call.
+ *   n          >= 1, with the padded size npad = ceil(n / ts) ts below
+ *              2^32 / max(ts, 1016) (4.2 million at tile 768; the kernels
+ *              index with 32-bit offsets): EINVAL above; device memory
+ *              bounds n far lower (ENOMEM).
  *   outputs    host memory unless stated otherwise.
  *   streams    all work is queued on the stream given to exageo_create; a call
  *              returns after synchronising that stream only when it has to

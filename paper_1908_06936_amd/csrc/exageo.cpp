@@ -200,6 +200,17 @@ exageo_status fail(exageo_ctx* c, exageo_status st, const char* fmt, ...) {
   return st;
 }
 
+// Largest n the kernels' index arithmetic allows at tile size ts: the GEMM
+// cores take 32-bit per-thread byte offsets (up to 127 rows of a leading
+// dimension npad, 127 * 8 npad < 2^32) and the mixed LAUUM divides k < npad by
+// ts through a reciprocal that is exact while npad ts < 2^32.  Device memory
+// holds n far below either bound (4.2 million at tile 768).
+bool n_fits(int64_t n, int64_t ts) {
+  if (n > (int64_t)INT32_MAX) return false;
+  const int64_t npad = (n + ts - 1) / ts * ts;
+  return npad < ((int64_t)1 << 32) / std::max<int64_t>(ts, 127 * 8);
+}
+
 #define HIPCHK(c, expr)                                                                               \
   do {                                                                                               \
     hipError_t e_ = (expr);                                                                          \
@@ -976,7 +987,7 @@ static exageo_status loglik_common(exageo_ctx* c, int64_t n, const double* x, co
   if (n < 1 || !x || !y || !z || !theta_ok(theta) || !loglik || (want_grad && !grad))
     return fail(c, EXAGEO_EINVAL, "loglik: invalid argument");
   if (precision != EXAGEO_FP64 && precision != EXAGEO_MIXED) return fail(c, EXAGEO_EINVAL, "unknown precision");
-  if (n > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n too large");
+  if (!n_fits(n, c->ts)) return fail(c, EXAGEO_EINVAL, "n too large for tile size %lld", (long long)c->ts);
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
   if (precision == EXAGEO_MIXED && c->dst_band > 0)
     return fail(c, EXAGEO_EINVAL, "the DST approximation runs in FP64 only");
@@ -1040,6 +1051,7 @@ exageo_status exageo_simulate(exageo_ctx* c, int64_t n, const double* x, const d
   c->err.clear();
   if (info) *info = 0;
   if (n < 1 || !x || !y || !e || !z || !theta_ok(theta)) return fail(c, EXAGEO_EINVAL, "simulate: invalid argument");
+  if (!n_fits(n, c->ts)) return fail(c, EXAGEO_EINVAL, "n too large for tile size %lld", (long long)c->ts);
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
   Plan p = make_plan(n, c->ts, 0);
   exageo_status st = ensure_ws(c, p);
@@ -1184,7 +1196,7 @@ exageo_status exageo_predict(exageo_ctx* c, int64_t n, const double* x, const do
   if (info) *info = 0;
   if (n < 1 || !x || !y || !z || !theta_ok(theta) || m < 0 || (m > 0 && (!xnew || !ynew || !mean)))
     return fail(c, EXAGEO_EINVAL, "predict: invalid argument");
-  if (n > (int64_t)INT32_MAX || m > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n or m too large");
+  if (!n_fits(n, c->ts) || m > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n or m too large");
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
   Plan p = make_plan(n, c->ts, 1, EXAGEO_FP64);  // the gradient plan: its staging holds the kriging blocks
   exageo_status st = ensure_ws(c, p);
@@ -1231,7 +1243,7 @@ exageo_status exageo_fisher(exageo_ctx* c, int64_t n, const double* x, const dou
   c->err.clear();
   if (info) *info = 0;
   if (n < 1 || !x || !y || !theta_ok(theta) || !fisher) return fail(c, EXAGEO_EINVAL, "fisher: invalid argument");
-  if (n > (int64_t)INT32_MAX) return fail(c, EXAGEO_EINVAL, "n too large");
+  if (!n_fits(n, c->ts)) return fail(c, EXAGEO_EINVAL, "n too large for tile size %lld", (long long)c->ts);
   if (c->dst_band > 0) return fail(c, EXAGEO_EINVAL, "the Fisher information is computed for the exact covariance only");
   if (set_device(c) != EXAGEO_OK) return EXAGEO_EDEVICE;
   const bool nug = c->nugget > 0.0;  // B_sigma2 is then not I / sigma2

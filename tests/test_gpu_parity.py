@@ -322,6 +322,25 @@ def test_statuses(exa, ctx256):
         exa.Context(ts=200)
 
 
+def test_n_beyond_index_range(exa, ctx256):
+    # a padded size beyond what the kernels' 32-bit offsets address is refused
+    # before any buffer is read (the four-element buffers are never touched)
+    import ctypes
+
+    from paper_1908_06936_amd import _lib
+
+    X, Y, Z = dev([0.1, 0.2, 0.3, 0.4]), dev([0.4, 0.3, 0.2, 0.1]), dev([1.0, 0.5, -0.5, 0.2])
+    ll, info = ctypes.c_double(0.0), ctypes.c_int64(0)
+    for n_big in ((1 << 32) // 1016 + 1, (1 << 31) - 1):
+        st = ctx256._lib.exageo_loglik(ctx256._h, n_big, ctypes.c_void_p(X.data_ptr()),
+                                       ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(Z.data_ptr()),
+                                       _lib.darr([1.0, 0.1, 0.5]), 0, ctypes.byref(ll), ctypes.byref(info))
+        assert st == exa.EINVAL
+    # the context still works afterwards
+    x, y = inputgen.jittered_grid(10, seed=0)
+    assert ctx256.loglik_status(dev(x), dev(y), dev(inputgen.normals(100)), [1.0, 0.1, 0.5])[0] == 0
+
+
 # ------------------------------------------------------------ MLE
 @pytest.mark.parametrize("method", ["dfo", "lbfgsb"])
 def test_mle_config1(orc, ctx768, method):
