@@ -118,3 +118,24 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_tile_index_reciprocal_is_exact_in_range():
+    # The mixed FP64 LAUUM takes the tile index k / ts as the high half of
+    # k m, m = floor(2^32 / ts) + 1, and the entry points keep k ts < 2^32.
+    # a m / 2^32 never falls below a / ts and is nondecreasing in a, so the
+    # quotient is exact on a whole block [q ts, q ts + ts - 1] once it is exact
+    # at the block's last element: check that element for every q in range,
+    # for every tile size the library accepts.
+    import numpy as np
+
+    src = open(os.path.join(ROOT, "paper_1908_06936_amd", "csrc", "common.h")).read()
+    assert "m((uint32_t)(0x100000000ull / (uint64_t)d + 1))" in src and "__umulhi(a, m)" in src
+    for d in range(128, 4097, 128):
+        m = (1 << 32) // d + 1
+        assert m < (1 << 32)
+        amax = ((1 << 32) - 1) // d  # largest a with a d < 2^32
+        q = np.arange(0, amax // d + 1, dtype=np.uint64)
+        a = np.minimum(q * np.uint64(d) + np.uint64(d - 1), np.uint64(amax))
+        got = (a * np.uint64(m)) >> np.uint64(32)
+        assert np.array_equal(got, a // np.uint64(d)), d
