@@ -139,3 +139,22 @@ def test_tile_index_reciprocal_is_exact_in_range():
         a = np.minimum(q * np.uint64(d) + np.uint64(d - 1), np.uint64(amax))
         got = (a * np.uint64(m)) >> np.uint64(32)
         assert np.array_equal(got, a // np.uint64(d)), d
+
+
+def test_profile_summaries_state_runnable_commands():
+    # every committed rocprofv3 summary gives the command that made it; the
+    # profiled program is the committed bench.py and every option it passes
+    # is one bench.py still accepts
+    prof = os.path.join(ROOT, "profiles")
+    bench_src = open(os.path.join(ROOT, "bench.py")).read()
+    accepted = set(re.findall(r'add_argument\("(--[a-z0-9-]+)"', bench_src))
+    files = sorted(f for f in os.listdir(prof) if f.endswith((".md", ".txt")))
+    assert files
+    for f in files:
+        cmds = re.findall(r"rocprofv3 [^\n`]*", open(os.path.join(prof, f)).read())
+        assert cmds, f
+        for c in cmds:
+            prog = c.split(" -- ", 1)[1].split()
+            assert prog[0] == "python3" and prog[1].endswith("/bench.py"), (f, c)
+            for opt in (a for a in prog[2:] if a.startswith("--")):
+                assert opt in accepted, (f, opt)
